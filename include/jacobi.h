@@ -1,0 +1,159 @@
+/*
+ * jacobi.h -- C ABI of libjacobi, a dense Jacobi solver for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method (Margaris, Souravlas & Roumeliotis, "Parallel implementations of
+ * the Jacobi linear algebraic systems solver", sec. 2): for A X = B with
+ * alpha_ii != 0, starting from X^0, repeat the sweep
+ *
+ *     x_i^(k) = ( beta_i - sum_{j != i} alpha_ij x_j^(k-1) ) / alpha_ii
+ *
+ * (the component equation of sec. 2; in matrix form X^(k) = T X^(k-1) + C
+ * with T = D^-1 (L + U), C = D^-1 B) until the distance between consecutive
+ * iterates falls below tol or the iteration cap L is reached (the serial
+ * pseudocode of sec. 2).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major with a leading dimension (elements, >= columns).
+ *     A is n x n, B and X are n x k (k right-hand sides, k >= 1).
+ *   - Unless stated otherwise, matrix and vector pointers are DEVICE pointers
+ *     owned by the caller.  The library never keeps a pointer after the call
+ *     returns.
+ *   - Calls are synchronous with respect to the stream passed in: work is
+ *     enqueued on that stream, the call waits for it, and outputs are valid on
+ *     return.  A NULL stream is the device's null stream.
+ *   - Errors are reported as return codes; no C++ exception crosses the ABI.
+ *     jacobi_last_error() gives a thread-local message for the last failure.
+ *   - Input validation happens before any sweep writes X: a validation error
+ *     leaves X untouched.
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;
+
+typedef enum {
+    JACOBI_OK = 0,                   /* converged: distance < tol                      */
+    JACOBI_NOT_CONVERGED = 1,        /* cap L reached (sec. 2, pseudocode step 3)      */
+    JACOBI_DIVERGED = 2,             /* distance became NaN or Inf                     */
+    JACOBI_PENDING = 3,              /* serving: not finished yet                      */
+    JACOBI_CANCELLED = 4,            /* serving: server destroyed before completion    */
+    JACOBI_ERR_INVALID_ARG = -1,     /* bad size, pointer, tolerance, cap or option    */
+    JACOBI_ERR_ZERO_DIAGONAL = -2,   /* some alpha_ii == 0 (sec. 2); bad_index = i     */
+    JACOBI_ERR_NONFINITE_INPUT = -3, /* NaN/Inf on the diagonal, in B or in X0         */
+    JACOBI_ERR_OUT_OF_MEMORY = -4,   /* device workspace could not be allocated        */
+    JACOBI_ERR_DEVICE = -5,          /* a HIP runtime call failed                      */
+    JACOBI_ERR_REJECTED = -6,        /* serving: request can never fit the HBM budget  */
+    JACOBI_ERR_INTERNAL = -7         /* unexpected internal failure                    */
+} jacobi_status;
+
+typedef enum {
+    JACOBI_F64 = 0,   /* double                                      */
+    JACOBI_F32 = 1,   /* float                                       */
+    JACOBI_BF16 = 2   /* bfloat16 (upper half of a binary32), A only */
+} jacobi_dtype;
+
+typedef enum {
+    JACOBI_NORM_INF = 0, /* max_i,c |x^(k) - x^(k-1)|                                  */
+    JACOBI_NORM_L2 = 1   /* Euclidean distance over all n*k entries (sec. 2, sec. 3.1) */
+} jacobi_norm;
+
+typedef enum {
+    JACOBI_MODE_PLAIN = 0,  /* Jacobi sweeps on A as given                                */
+    JACOBI_MODE_REFINE = 1  /* FP64 system; sweeps on a reduced-precision copy of A inside
+                               iterative refinement (residual and update in FP64)         */
+} jacobi_mode;
+
+/* Solver options.  Fill with jacobi_options_default() and change fields.
+ *
+ * PLAIN mode: stop after sweep k when distance_k < tol (strict, absolute;
+ *   sec. 2 pseudocode step (b)), or after max_iter sweeps.  tol = 0 runs exactly
+ *   max_iter sweeps (fixed-iteration mode).  max_iter = 0 returns X = X0.
+ * REFINE mode (A, B, X in FP64): outer loop r = B - A x (FP64), stop when
+ *   ||r||_2 < refine_tol * ||B||_2 (per system; a zero residual also stops);
+ *   otherwise solve A_lo d = r by Jacobi sweeps on A_lo = round(A) in
+ *   sweep_dtype (F32 or BF16) with FP32 accumulation, starting from d = 0 and
+ *   stopping when max|d^(j) - d^(j-1)| <= inner_rel_tol * max|d^(j)| or after
+ *   max_inner sweeps, then x += d in FP64.  At most max_outer corrections. */
+typedef struct {
+    double tol;             /* PLAIN: absolute threshold on the distance (default 1e-8)  */
+    int32_t max_iter;       /* PLAIN: iteration cap L (default 10000)                     */
+    int32_t norm;           /* jacobi_norm (default JACOBI_NORM_INF)                      */
+    int32_t mode;           /* jacobi_mode (default JACOBI_MODE_PLAIN)                    */
+    int32_t sweep_dtype;    /* REFINE: JACOBI_F32 or JACOBI_BF16 (default BF16)           */
+    double inner_rel_tol;   /* REFINE: inner relative stop (default 1e-3)                 */
+    int32_t max_inner;      /* REFINE: inner sweep cap per correction (default 200)       */
+    int32_t max_outer;      /* REFINE: correction cap (default 50)                        */
+    double refine_tol;      /* REFINE: ||r||_2 / ||B||_2 target (default 1e-10)           */
+    int32_t sync_every;     /* sweeps between host checks of the stop flag, 0 = adaptive  */
+    int32_t profile;        /* 1: time every sweep kernel with HIP events (see info)      */
+} jacobi_options;
+
+typedef struct {
+    int32_t status;           /* jacobi_status of this system                            */
+    int32_t iterations;       /* sweeps executed (REFINE: inner sweeps, all corrections)  */
+    int32_t outer_iterations; /* REFINE: residual evaluations; PLAIN: 0                  */
+    int32_t reserved;
+    int64_t bad_index;        /* first offending row for ZERO_DIAGONAL / NONFINITE, or -1 */
+    double final_delta;       /* distance of the last executed sweep (-1 if none)        */
+    double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */
+    double device_ms;         /* device time of the whole call (HIP events)              */
+    double sweep_kernel_ms;   /* profile=1: summed duration of the sweep kernels         */
+    int64_t sweep_kernel_launches; /* profile=1: number of sweep kernels timed           */
+} jacobi_info;
+
+typedef struct jacobi_ctx jacobi_ctx;
+
+/* Fill *opt with the defaults above (the paper's experiment values tol = 1e-8
+ * and L = 10000, sec. 4). */
+void jacobi_options_default(jacobi_options* opt);
+
+/* Create a context bound to HIP device `device`: it owns device workspaces
+ * (iterate ping-pong buffer, diagonal, stop-flag block) reused across calls.
+ * Calls on one context are serialised by an internal lock.  Returns
+ * JACOBI_ERR_INVALID_ARG for a bad device or NULL out. */
+jacobi_status jacobi_ctx_create(int32_t device, jacobi_ctx** out);
+jacobi_status jacobi_ctx_destroy(jacobi_ctx* ctx);
+
+/* Solve A X = B (sec. 2) for one dense system with k right-hand sides.
+ *
+ * ctx      context, or NULL for the per-device default context of the current device
+ * n, k     system size and number of right-hand sides (n >= 1, k >= 1)
+ * a_dtype  element type of A.  PLAIN: F64 => B, X0, X are double; F32 or BF16 =>
+ *          B, X0, X are float (BF16 A is widened to FP32, FP32 accumulation).
+ *          REFINE: must be F64 (A, B, X0, X double).
+ * A, lda   device matrix n x n, row-major, lda >= n
+ * B, ldb   device n x k, ldb >= k
+ * X0       device n x k initial approximation (leading dim ldx), NULL => zero;
+ *          may alias X
+ * X, ldx   device n x k output, ldx >= k
+ * opt      options, NULL => defaults
+ * stream   HIP stream of the caller (work is enqueued there; the call waits)
+ * info     optional host pointer receiving the outcome
+ *
+ * Returns the solve status (also info->status): OK, NOT_CONVERGED, DIVERGED,
+ * or an error.  On OK, X holds the iterate whose distance to its predecessor
+ * met the test; on NOT_CONVERGED, X^(L); on DIVERGED, the last (non-finite)
+ * iterate. */
+jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k, int32_t a_dtype,
+                           const void* A, int64_t lda, const void* B, int64_t ldb,
+                           const void* X0, void* X, int64_t ldx, const jacobi_options* opt,
+                           hipStream_t stream, jacobi_info* info);
+
+/* Human-readable name of a status code (static string). */
+const char* jacobi_status_string(int32_t status);
+
+/* Thread-local description of the last error raised in this thread ("" if none). */
+const char* jacobi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_H */

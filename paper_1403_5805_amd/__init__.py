@@ -1,0 +1,159 @@
+"""MI355X (gfx950) dense Jacobi solver: Python binding of libjacobi.
+
+The method is the Jacobi iteration for A X = B of Margaris, Souravlas and
+Roumeliotis (sec. 2: component equation and serial pseudocode).  Every step
+runs in the library's HIP kernels; this module only marshals torch device
+tensors and the current torch stream into the C ABI (include/jacobi.h).
+
+    import torch, paper_1403_5805_amd as jac
+    X, info = jac.solve(A, B, tol=1e-8, max_iter=10000)
+
+Defaults tol = 1e-8 and max_iter = 10000 are the paper's experiment values
+(sec. 4).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVALID_ARG,
+                   ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
+                   F64, NOT_CONVERGED, OK, PENDING, Info, Options)
+
+__all__ = ["solve", "status_string", "last_error", "Context",
+           "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
+           "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
+           "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def status_string(code: int) -> str:
+    return _lib.load().jacobi_status_string(int(code)).decode()
+
+
+def last_error() -> str:
+    return _lib.load().jacobi_last_error().decode()
+
+
+def _a_dtype(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype for A: {t.dtype}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ld(t) -> int:
+    """Leading dimension of a row-major 2-D view (unit column stride)."""
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError("vectors must be contiguous")
+        return 1
+    if t.stride(1) != 1:
+        raise ValueError("matrices must have unit column stride (row-major)")
+    return max(t.stride(0), t.shape[1])
+
+
+def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype="bf16",
+                 inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-10,
+                 sync_every=0, profile=False) -> Options:
+    o = Options()
+    _lib.load().jacobi_options_default(ctypes.byref(o))
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.norm = {"inf": 0, "l2": 1}[norm] if isinstance(norm, str) else int(norm)
+    o.mode = {"plain": 0, "refine": 1}[mode] if isinstance(mode, str) else int(mode)
+    o.sweep_dtype = ({"f32": F32, "bf16": BF16}[sweep_dtype]
+                     if isinstance(sweep_dtype, str) else int(sweep_dtype))
+    o.inner_rel_tol = float(inner_rel_tol)
+    o.max_inner = int(max_inner)
+    o.max_outer = int(max_outer)
+    o.refine_tol = float(refine_tol)
+    o.sync_every = int(sync_every)
+    o.profile = 1 if profile else 0
+    return o
+
+
+class Context:
+    """A solver context bound to one device (owns reusable workspaces)."""
+
+    def __init__(self, device: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        st = lib.jacobi_ctx_create(int(device), ctypes.byref(h))
+        if st != OK:
+            raise RuntimeError(f"jacobi_ctx_create: {status_string(st)} {last_error()}")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.load().jacobi_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream, device):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
+          raise_on_error: bool = False, **opts):
+    """Solve A X = B by Jacobi sweeps on the GPU.
+
+    A: (n, n) torch tensor on the GPU, float64 / float32 / bfloat16, unit column
+    stride (a row stride > n is honoured as the leading dimension).
+    B: (n,) or (n, k); float64 for float64 A (and in refine mode), else float32.
+    x0: initial approximation like B, or None for zero.
+    opts: tol, max_iter, norm ("inf" | "l2"), mode ("plain" | "refine"),
+    sweep_dtype ("f32" | "bf16"), inner_rel_tol, max_inner, max_outer,
+    refine_tol, sync_every, profile.
+    Returns (X, info dict).  X has B's shape.
+    """
+    torch = _torch()
+    lib = _lib.load()
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    n = A.shape[0]
+    vec = B.dim() == 1
+    k = 1 if vec else B.shape[1]
+    if B.shape[0] != n:
+        raise ValueError("B must have n rows")
+    if out is None:
+        out = torch.empty((n,) if vec else (n, k), dtype=B.dtype, device=B.device)
+    if x0 is not None and not vec and _ld(x0) != _ld(out):
+        x0 = x0.contiguous()
+        if _ld(out) != k:
+            raise ValueError("x0 and out must share a leading dimension")
+    o = make_options(**opts)
+    info = Info()
+    st = lib.jacobi_solve(ctx.handle if ctx else None, n, k, _a_dtype(A), _ptr(A), _ld(A),
+                          _ptr(B), _ld(B) if not vec else 1,
+                          _ptr(x0) if x0 is not None else None, _ptr(out),
+                          _ld(out) if not vec else 1, ctypes.byref(o),
+                          _stream_handle(stream, A.device), ctypes.byref(info))
+    d = info.as_dict()
+    d["status_name"] = status_string(st)
+    if st < 0:
+        d["error"] = last_error()
+        if raise_on_error:
+            raise RuntimeError(f"jacobi_solve failed: {d['status_name']}: {d['error']}")
+    return out, d
+

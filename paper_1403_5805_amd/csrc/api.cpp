@@ -1,0 +1,453 @@
+// Host runtime and C ABI of libjacobi: argument checks, device workspaces,
+// the sweep loop with its device stop flag, and iterative refinement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/jacobi.h"
+#include "ctx.h"
+#include "internal.h"
+
+using namespace jac;
+
+namespace jac {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+hipError_t DevBuf::ensure(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    if (p) {
+        hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    size_t want = std::max(b, (size_t)256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    bytes = want;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+jacobi_status ctx_init(jacobi_ctx* c, int device) {
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return JACOBI_ERR_DEVICE;
+    c->num_cus = prop.multiProcessorCount;
+    if (hipSetDevice(device) != hipSuccess) return JACOBI_ERR_DEVICE;
+    if (hipMalloc(&c->ctl, sizeof(Ctl)) != hipSuccess) return JACOBI_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&c->slots, 2 * sizeof(Slot)) != hipSuccess) return JACOBI_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&c->parts, 2 * sizeof(double) * kMaxParts) != hipSuccess)
+        return JACOBI_ERR_OUT_OF_MEMORY;
+    if (hipHostMalloc(&c->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+        return JACOBI_ERR_OUT_OF_MEMORY;
+    if (hipEventCreate(&c->ev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
+    if (hipEventCreate(&c->ev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
+    return JACOBI_OK;
+}
+
+void ctx_release(jacobi_ctx* c) {
+    hipSetDevice(c->device);
+    for (DevBuf* b : {&c->diag, &c->w0, &c->w1, &c->alo, &c->diag_lo, &c->xa, &c->xb, &c->r64,
+                      &c->rlo, &c->d0, &c->d1, &c->scal})
+        b->release();
+    if (c->ctl) hipFree(c->ctl);
+    if (c->slots) hipFree(c->slots);
+    if (c->parts) hipFree(c->parts);
+    if (c->h_ctl) hipHostFree(c->h_ctl);
+    if (c->ev_begin) hipEventDestroy(c->ev_begin);
+    if (c->ev_end) hipEventDestroy(c->ev_end);
+    for (auto& e : c->prof_ev) hipEventDestroy(e);
+    c->prof_ev.clear();
+}
+
+static std::mutex g_default_mu;
+static std::vector<jacobi_ctx*> g_default_ctx;
+
+jacobi_ctx* default_ctx(jacobi_status* st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *st = JACOBI_ERR_DEVICE;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> g(g_default_mu);
+    if ((int)g_default_ctx.size() <= dev) g_default_ctx.resize(dev + 1, nullptr);
+    if (!g_default_ctx[dev]) {
+        jacobi_ctx* c = new (std::nothrow) jacobi_ctx();
+        if (!c) {
+            *st = JACOBI_ERR_OUT_OF_MEMORY;
+            return nullptr;
+        }
+        jacobi_status s = ctx_init(c, dev);
+        if (s != JACOBI_OK) {
+            ctx_release(c);
+            delete c;
+            *st = s;
+            return nullptr;
+        }
+        g_default_ctx[dev] = c;
+    }
+    *st = JACOBI_OK;
+    return g_default_ctx[dev];
+}
+
+static int kpad_for(int64_t k) {
+    if (k <= 32) {
+        int kt = 1;
+        while (kt < k) kt <<= 1;
+        return kt;
+    }
+    return (int)((k + 31) / 32 * 32);
+}
+
+static size_t dtype_bytes(int32_t d) { return d == JACOBI_F64 ? 8 : (d == JACOBI_F32 ? 4 : 2); }
+
+#define HIP_TRY(expr)                                                               \
+    do {                                                                            \
+        hipError_t _e = (expr);                                                     \
+        if (_e != hipSuccess) {                                                     \
+            set_error("%s failed: %s", #expr, hipGetErrorString(_e));               \
+            return _e == hipErrorOutOfMemory ? JACOBI_ERR_OUT_OF_MEMORY             \
+                                             : JACOBI_ERR_DEVICE;                   \
+        }                                                                           \
+    } while (0)
+
+jacobi_status check_common(int64_t n, int64_t k, int32_t a_dtype, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* X, int64_t ldx,
+                           const jacobi_options& o) {
+    if (n < 1 || k < 1 || lda < n || ldb < k || ldx < k || !A || !B || !X) {
+        set_error("invalid sizes or null pointer (n=%lld k=%lld lda=%lld ldb=%lld ldx=%lld)",
+                  (long long)n, (long long)k, (long long)lda, (long long)ldb, (long long)ldx);
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    if (a_dtype < JACOBI_F64 || a_dtype > JACOBI_BF16) {
+        set_error("unknown a_dtype %d", a_dtype);
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    if (std::isnan(o.tol) || o.tol < 0.0 || o.max_iter < 0 ||
+        (o.norm != JACOBI_NORM_INF && o.norm != JACOBI_NORM_L2) ||
+        (o.mode != JACOBI_MODE_PLAIN && o.mode != JACOBI_MODE_REFINE) || o.sync_every < 0) {
+        set_error("invalid options (tol, max_iter, norm, mode or sync_every)");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    if (n > (int64_t)INT32_MAX || k > 4096) {
+        set_error("size out of supported range");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    return JACOBI_OK;
+}
+
+static jacobi_status validation_status(const Ctl& h, int64_t* bad) {
+    const int64_t bz = h.bad_zero, bn = h.bad_nonfinite, br = h.bad_rhs;
+    if (bz != INT64_MAX || bn != INT64_MAX) {
+        if (bz < bn) {
+            *bad = bz;
+            return JACOBI_ERR_ZERO_DIAGONAL;
+        }
+        *bad = bn;
+        return JACOBI_ERR_NONFINITE_INPUT;
+    }
+    *bad = br;
+    return JACOBI_ERR_NONFINITE_INPUT;
+}
+
+static double bits_to_double(uint64_t b) {
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// Run Jacobi sweeps on the prepared buffers until the device stop flag is set
+// or `cap` sweeps ran.  bufs[0] holds x^(0); sweep s reads bufs[(s-1)&1] and
+// writes bufs[s&1].  Returns the stop code and the number of sweeps whose
+// result is final (K); the final iterate lives in bufs[K & 1].
+jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const LaunchCfg& cfg,
+                         void* bufs[2], int32_t cap, int32_t sync_every, int profile,
+                         hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
+                         double* xmax_out, double* kernel_ms, int64_t* launches) {
+    int32_t done = 0;
+    int32_t chunk = sync_every > 0 ? sync_every : 4;
+    *stop_out = STOP_RUNNING;
+    if (profile && (int)c->prof_ev.size() < 2 * 512) {
+        while ((int)c->prof_ev.size() < 2 * 512) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            c->prof_ev.push_back(e);
+        }
+    }
+    const int32_t max_chunk = profile ? 512 : 256;
+    while (done < cap) {
+        int32_t S = std::min(chunk, cap - done);
+        if (profile) S = std::min(S, max_chunk);
+        for (int32_t q = 1; q <= S; ++q) {
+            const int32_t sw = done + q;
+            args.sweep = sw;
+            args.seq = sw;
+            args.xin = bufs[(sw - 1) & 1];
+            args.xout = bufs[sw & 1];
+            if (profile) HIP_TRY(hipEventRecord(c->prof_ev[2 * (q - 1)], s));
+            HIP_TRY(launch_sweep(a_dtype, args, cfg, s));
+            if (profile) HIP_TRY(hipEventRecord(c->prof_ev[2 * (q - 1) + 1], s));
+        }
+        HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const Ctl& h = *c->h_ctl;
+        if (profile) {
+            const int32_t ran = h.stop != STOP_RUNNING ? std::max(0, h.stop_sweep - done) : S;
+            for (int32_t q = 1; q <= ran; ++q) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, c->prof_ev[2 * (q - 1)], c->prof_ev[2 * (q - 1) + 1]));
+                *kernel_ms += ms;
+                *launches += 1;
+            }
+        }
+        if (h.stop != STOP_RUNNING) {
+            *stop_out = h.stop;
+            *k_out = h.stop == STOP_INVALID ? 0 : h.stop_sweep;
+            *delta_out = bits_to_double(h.last_delta_bits);
+            *xmax_out = bits_to_double(h.last_xmax_bits);
+            return JACOBI_OK;
+        }
+        done += S;
+        if (sync_every == 0) chunk = std::min(chunk * 2, 256);
+    }
+    if (cap == 0) {
+        HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->h_ctl->stop == STOP_INVALID) *stop_out = STOP_INVALID;
+        *delta_out = -1.0;
+    } else {
+        *delta_out = bits_to_double(c->h_ctl->last_delta_bits);
+        *xmax_out = bits_to_double(c->h_ctl->last_xmax_bits);
+    }
+    *k_out = cap;
+    return JACOBI_OK;
+}
+
+static jacobi_status solve_plain(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_dtype,
+                                 const void* A, int64_t lda, const void* B, int64_t ldb,
+                                 const void* X0, void* X, int64_t ldx, const jacobi_options& o,
+                                 hipStream_t s, jacobi_info* info) {
+    const int kp = kpad_for(k);
+    const size_t sx = a_dtype == JACOBI_F64 ? 8 : 4;
+    HIP_TRY(c->diag.ensure(sx * n));
+    HIP_TRY(c->w0.ensure(sx * n * kp));
+    HIP_TRY(c->w1.ensure(sx * n * kp));
+    const LaunchCfg cfg = default_cfg(a_dtype, n, (int)k, c->num_cus);
+    if (cfg.grid * ((k + 31) / 32) > kMaxParts) {
+        set_error("grid too large");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    HIP_TRY(hipEventRecord(c->ev_begin, s));
+    HIP_TRY(launch_init_ctl(c->ctl, c->slots, 1, s));
+    HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, c->diag.p, c->w0.p,
+                         c->w1.p, c->ctl, s));
+    SweepArgs a{};
+    a.A = A;
+    a.lda = lda;
+    a.B = B;
+    a.ldb = ldb;
+    a.diag = c->diag.p;
+    a.n = n;
+    a.k = (int)k;
+    a.kpad = kp;
+    a.ldin = kp;
+    a.ldout = kp;
+    a.ctl = c->ctl;
+    a.slots = c->slots;
+    a.parts = c->parts;
+    a.tol = o.tol;
+    a.test = TEST_ABS;
+    a.norm = o.norm;
+    const size_t ea = dtype_bytes(a_dtype);
+    a.aligned = (((uintptr_t)A % 16) == 0 && ((size_t)lda * ea) % 16 == 0) ? 1 : 0;
+    void* bufs[2] = {c->w0.p, c->w1.p};
+    uint32_t stop = 0;
+    int32_t K = 0;
+    double delta = -1.0, xmax = 0.0, kms = 0.0;
+    int64_t launches = 0;
+    jacobi_status st = run_sweeps(c, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every, o.profile,
+                                  s, &stop, &K, &delta, &xmax, &kms, &launches);
+    if (st != JACOBI_OK) return st;
+    info->bad_index = -1;
+    if (stop == STOP_INVALID) {
+        jacobi_status vs = validation_status(*c->h_ctl, &info->bad_index);
+        info->status = vs;
+        info->iterations = 0;
+        info->final_delta = -1.0;
+        HIP_TRY(hipStreamSynchronize(s));
+        set_error("input validation failed at row %lld", (long long)info->bad_index);
+        return vs;
+    }
+    HIP_TRY(launch_copy_rows((int)sx, bufs[K & 1], kp, X, ldx, n, (int)k, s));
+    HIP_TRY(hipEventRecord(c->ev_end, s));
+    HIP_TRY(hipEventSynchronize(c->ev_end));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_begin, c->ev_end));
+    info->device_ms = ms;
+    info->iterations = K;
+    info->final_delta = K > 0 ? delta : -1.0;
+    info->sweep_kernel_ms = kms;
+    info->sweep_kernel_launches = launches;
+    jacobi_status res = JACOBI_NOT_CONVERGED;
+    if (stop == STOP_CONVERGED) res = JACOBI_OK;
+    if (stop == STOP_DIVERGED) res = JACOBI_DIVERGED;
+    info->status = res;
+    return res;
+}
+
+}  // namespace jac
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+void jacobi_options_default(jacobi_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->max_iter = 10000;
+    o->norm = JACOBI_NORM_INF;
+    o->mode = JACOBI_MODE_PLAIN;
+    o->sweep_dtype = JACOBI_BF16;
+    o->inner_rel_tol = 1e-3;
+    o->max_inner = 200;
+    o->max_outer = 50;
+    o->refine_tol = 1e-10;
+    o->sync_every = 0;
+    o->profile = 0;
+}
+
+jacobi_status jacobi_ctx_create(int32_t device, jacobi_ctx** out) {
+    try {
+        if (!out) return JACOBI_ERR_INVALID_ARG;
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess) {
+            set_error("hipGetDeviceCount failed");
+            return JACOBI_ERR_DEVICE;
+        }
+        if (device < 0 || device >= count) {
+            set_error("device %d out of range (%d devices)", device, count);
+            return JACOBI_ERR_INVALID_ARG;
+        }
+        jacobi_ctx* c = new (std::nothrow) jacobi_ctx();
+        if (!c) return JACOBI_ERR_OUT_OF_MEMORY;
+        jacobi_status s = ctx_init(c, device);
+        if (s != JACOBI_OK) {
+            ctx_release(c);
+            delete c;
+            return s;
+        }
+        *out = c;
+        return JACOBI_OK;
+    } catch (...) {
+        return JACOBI_ERR_INTERNAL;
+    }
+}
+
+jacobi_status jacobi_ctx_destroy(jacobi_ctx* c) {
+    try {
+        if (!c) return JACOBI_ERR_INVALID_ARG;
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            ctx_release(c);
+        }
+        delete c;
+        return JACOBI_OK;
+    } catch (...) {
+        return JACOBI_ERR_INTERNAL;
+    }
+}
+
+jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k, int32_t a_dtype, const void* A,
+                           int64_t lda, const void* B, int64_t ldb, const void* X0, void* X,
+                           int64_t ldx, const jacobi_options* opt, hipStream_t stream,
+                           jacobi_info* info) {
+    try {
+        jacobi_info local;
+        if (!info) info = &local;
+        std::memset(info, 0, sizeof(*info));
+        info->status = JACOBI_ERR_INVALID_ARG;
+        info->bad_index = -1;
+        info->final_delta = -1.0;
+        info->rel_residual = -1.0;
+        jacobi_options o;
+        jacobi_options_default(&o);
+        if (opt) o = *opt;
+        jacobi_status st = check_common(n, k, a_dtype, A, lda, B, ldb, X, ldx, o);
+        if (st != JACOBI_OK) return (jacobi_status)(info->status = st);
+        if (o.mode == JACOBI_MODE_REFINE && a_dtype != JACOBI_F64) {
+            set_error("REFINE mode needs an FP64 system");
+            return (jacobi_status)(info->status = JACOBI_ERR_INVALID_ARG);
+        }
+        jacobi_ctx* c = ctx;
+        if (!c) {
+            c = default_ctx(&st);
+            if (!c) return (jacobi_status)(info->status = st);
+        }
+        std::lock_guard<std::mutex> g(c->mu);
+        if (hipSetDevice(c->device) != hipSuccess) {
+            set_error("hipSetDevice(%d) failed", c->device);
+            return (jacobi_status)(info->status = JACOBI_ERR_DEVICE);
+        }
+        if (o.mode == JACOBI_MODE_REFINE)
+            st = solve_refine(c, n, k, A, lda, B, ldb, X0, X, ldx, o, stream, info);
+        else
+            st = solve_plain(c, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, stream, info);
+        info->status = st;
+        return st;
+    } catch (...) {
+        set_error("internal exception");
+        if (info) info->status = JACOBI_ERR_INTERNAL;
+        return JACOBI_ERR_INTERNAL;
+    }
+}
+
+const char* jacobi_status_string(int32_t s) {
+    switch (s) {
+        case JACOBI_OK: return "OK";
+        case JACOBI_NOT_CONVERGED: return "NOT_CONVERGED";
+        case JACOBI_DIVERGED: return "DIVERGED";
+        case JACOBI_PENDING: return "PENDING";
+        case JACOBI_CANCELLED: return "CANCELLED";
+        case JACOBI_ERR_INVALID_ARG: return "ERR_INVALID_ARG";
+        case JACOBI_ERR_ZERO_DIAGONAL: return "ERR_ZERO_DIAGONAL";
+        case JACOBI_ERR_NONFINITE_INPUT: return "ERR_NONFINITE_INPUT";
+        case JACOBI_ERR_OUT_OF_MEMORY: return "ERR_OUT_OF_MEMORY";
+        case JACOBI_ERR_DEVICE: return "ERR_DEVICE";
+        case JACOBI_ERR_REJECTED: return "ERR_REJECTED";
+        case JACOBI_ERR_INTERNAL: return "ERR_INTERNAL";
+    }
+    return "UNKNOWN";
+}
+
+const char* jacobi_last_error(void) { return jac::g_last_error.c_str(); }
+
+}  // extern "C"

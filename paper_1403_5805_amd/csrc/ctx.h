@@ -1,0 +1,58 @@
+// Solver context: per-device workspaces reused across calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/jacobi.h"
+#include "internal.h"
+
+namespace jac {
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t b);
+    void release();
+};
+
+}  // namespace jac
+
+struct jacobi_ctx {
+    int device = 0;
+    int num_cus = 256;
+    std::mutex mu;
+    jac::Ctl* ctl = nullptr;      // device control block
+    jac::Slot* slots = nullptr;   // device reduction slots [2]
+    double* parts = nullptr;      // device partial sums [2][kMaxParts]
+    jac::Ctl* h_ctl = nullptr;    // pinned host mirror of ctl
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    std::vector<hipEvent_t> prof_ev;
+    // plain solve
+    jac::DevBuf diag, w0, w1;
+    // refinement
+    jac::DevBuf alo, diag_lo, xa, xb, r64, rlo, d0, d1, scal;
+};
+
+namespace jac {
+
+void set_error(const char* fmt, ...);
+jacobi_status ctx_init(jacobi_ctx* c, int device);
+void ctx_release(jacobi_ctx* c);
+jacobi_ctx* default_ctx(jacobi_status* st);
+jacobi_status check_common(int64_t n, int64_t k, int32_t a_dtype, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* X, int64_t ldx,
+                           const jacobi_options& o);
+jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const LaunchCfg& cfg,
+                         void* bufs[2], int32_t cap, int32_t sync_every, int profile,
+                         hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
+                         double* xmax_out, double* kernel_ms, int64_t* launches);
+jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
+                           const jacobi_options& o, hipStream_t s, jacobi_info* info);
+
+}  // namespace jac

@@ -1,0 +1,114 @@
+// Internal declarations shared by the kernels and the host runtime of libjacobi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jac {
+
+// Stop codes written by the device into Ctl::stop.
+enum : uint32_t {
+    STOP_RUNNING = 0,
+    STOP_CONVERGED = 1,  // distance met the test (or residual target reached)
+    STOP_DIVERGED = 2,   // distance NaN/Inf
+    STOP_INVALID = 3     // validation failed: sweeps must not run
+};
+
+// How the decider judges a sweep.
+enum : int32_t {
+    TEST_ABS = 0,     // distance < tol (strict), sec. 2 pseudocode step (b)
+    TEST_REL = 1,     // distance <= rel * max|x_new| (inner refinement sweeps)
+    TEST_RESID = 2    // residual pass: ||r||_2 < rel * ||b||_2, or ||r||_2 == 0
+};
+
+// Per-solve control block on the device.  The host copies it back once per
+// group of sweeps.
+struct alignas(64) Ctl {
+    uint32_t stop;           // STOP_*
+    int32_t stop_sweep;      // sweep number at which stop was decided
+    int32_t sweeps_done;     // last sweep whose decision ran
+    int32_t pad0;
+    uint64_t last_delta_bits;  // double bits of the last decided distance
+    uint64_t last_xmax_bits;   // double bits of max|x_new| of the last sweep
+    int64_t bad_zero;        // min row with alpha_ii == 0         (INT64_MAX if none)
+    int64_t bad_nonfinite;   // min row with non-finite alpha_ii   (INT64_MAX if none)
+    int64_t bad_rhs;         // min row with non-finite B or X0    (INT64_MAX if none)
+    uint32_t setup_ticket;
+    uint32_t pad1;
+};
+
+// Per-sweep reduction slot (two of them, used alternately).
+struct alignas(64) Slot {
+    uint64_t dmax_bits;  // atomic max of |x_new - x_old| (double bits, >= 0; NaN wins)
+    uint64_t xmax_bits;  // atomic max of |x_new|
+    uint32_t ticket;     // workgroups finished
+    uint32_t pad;
+};
+
+constexpr int kMaxParts = 1 << 16;  // per-slot partial sums (one per workgroup)
+
+// Arguments of one sweep (or residual) launch.
+struct SweepArgs {
+    const void* A;
+    int64_t lda;
+    const void* B;     // TX, n x k (ldb)
+    int64_t ldb;
+    const void* xin;   // TX, n x k (ldin)
+    int64_t ldin;
+    void* xout;        // TX (sweep) or double (residual: updated x)
+    int64_t ldout;
+    const void* diag;  // TX[n]
+    int64_t n;
+    int32_t k;
+    int32_t sweep;     // logical sweep number reported to the host, 1-based
+    int32_t seq;       // launch number within the current phase (selects the slot)
+    int32_t aligned;   // 1: rows of A are 16-byte aligned (vector loads allowed)
+    int64_t chunk;     // columns of x staged in LDS at once
+    int32_t kpad;      // leading dimension of the iterate buffers (>= k)
+    Ctl* ctl;
+    Slot* slots;       // [2]
+    double* parts;     // [2][kMaxParts]
+    double tol;        // TEST_ABS threshold
+    double rel;        // TEST_REL / TEST_RESID factor
+    double bnorm;      // TEST_RESID: ||b||_2
+    int32_t test;      // TEST_*
+    int32_t norm;      // 0 inf, 1 l2
+    // residual pass extras
+    const float* dlt;  // correction d (float, ld k) added to xin while staging, or null
+    double* r64;       // residual out (double, ld k)
+    float* rlo;        // residual out (float, ld k)
+};
+
+// Host-side launch configuration chosen per call.
+struct LaunchCfg {
+    int waves;     // waves per workgroup
+    int rows;      // rows per wave
+    int64_t chunk; // columns of x staged in LDS at once
+    int grid;      // workgroups along rows
+};
+
+// Kernel launchers (defined in sweep.hip).  Return hipSuccess or the launch error.
+hipError_t launch_init_ctl(Ctl* ctl, Slot* slots, int full, hipStream_t s);
+hipError_t launch_setup(int32_t a_dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        const void* X0, int64_t ldx0, int64_t n, int32_t k, int32_t kpad,
+                        void* diag, void* w0, void* w1, Ctl* ctl, hipStream_t s);
+hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cfg,
+                        hipStream_t s);
+hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
+                          int64_t ldo, hipStream_t s);
+hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64_t n,
+                              void* out, hipStream_t s);
+hipError_t launch_bnorm(const double* B, int64_t ldb, int64_t n, int32_t k, double* out,
+                        hipStream_t s);
+hipError_t launch_copy_rows(int32_t elem_bytes, const void* src, int64_t lds, void* dst,
+                            int64_t ldd, int64_t n, int32_t k, hipStream_t s);
+hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t n, int32_t k,
+                            hipStream_t s);
+
+// Default launch configuration for a sweep of this shape.
+LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus);
+LaunchCfg residual_cfg(int64_t n, int32_t k, int num_cus);
+size_t sweep_lds_bytes(int32_t a_dtype, int32_t k, const LaunchCfg& cfg);
+
+}  // namespace jac

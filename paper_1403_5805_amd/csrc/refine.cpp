@@ -1,0 +1,203 @@
+// Mixed-precision iterative refinement around the Jacobi sweep.
+//
+// The system of record is FP64 (A, B, X).  A reduced-precision copy A_lo
+// (FP32 or BF16, round to nearest even) is built on the device once per call.
+// Outer loop:   r = B - A x            (FP64 residual pass over FP64 A)
+//               stop if ||r||_2 < refine_tol * ||B||_2
+//               solve A_lo d = r       (Jacobi sweeps, FP32 accumulation,
+//                                       d^0 = 0, relative stop)
+//               x = x + d              (FP64, fused into the next residual pass)
+// The residual and the update are the only FP64 steps on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace jac {
+
+#define HIP_TRY(expr)                                                               \
+    do {                                                                            \
+        hipError_t _e = (expr);                                                     \
+        if (_e != hipSuccess) {                                                     \
+            set_error("%s failed: %s", #expr, hipGetErrorString(_e));               \
+            return _e == hipErrorOutOfMemory ? JACOBI_ERR_OUT_OF_MEMORY             \
+                                             : JACOBI_ERR_DEVICE;                   \
+        }                                                                           \
+    } while (0)
+
+static int kpad_of(int64_t k) {
+    if (k <= 32) {
+        int kt = 1;
+        while (kt < k) kt <<= 1;
+        return kt;
+    }
+    return (int)((k + 31) / 32 * 32);
+}
+
+static double bits_to_double(uint64_t b) {
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
+                           const jacobi_options& o, hipStream_t s, jacobi_info* info) {
+    const int32_t lo = o.sweep_dtype;
+    if ((lo != JACOBI_F32 && lo != JACOBI_BF16) || !(o.inner_rel_tol >= 0.0) ||
+        !(o.refine_tol >= 0.0) || o.max_inner < 1 || o.max_outer < 0) {
+        set_error("invalid refinement options");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    const int kp = kpad_of(k);
+    const size_t elo = lo == JACOBI_F32 ? 4 : 2;
+    const int64_t ld_lo = (n + 7) / 8 * 8;  // 16-byte aligned rows for both FP32 and BF16
+    HIP_TRY(c->diag.ensure(8 * n));
+    HIP_TRY(c->xa.ensure(8 * n * kp));
+    HIP_TRY(c->xb.ensure(8 * n * kp));
+    HIP_TRY(c->r64.ensure(8 * n * kp));
+    HIP_TRY(c->rlo.ensure(4 * n * kp));
+    HIP_TRY(c->d0.ensure(4 * n * kp));
+    HIP_TRY(c->d1.ensure(4 * n * kp));
+    HIP_TRY(c->diag_lo.ensure(4 * n));
+    HIP_TRY(c->scal.ensure(64));
+    HIP_TRY(c->alo.ensure(elo * (size_t)n * ld_lo));
+
+    HIP_TRY(hipEventRecord(c->ev_begin, s));
+    // Validation of the FP64 system and x^(0) into xa.
+    HIP_TRY(launch_init_ctl(c->ctl, c->slots, 1, s));
+    HIP_TRY(launch_setup(JACOBI_F64, A, lda, B, ldb, X0, ldx, n, (int)k, kp, c->diag.p, c->xa.p,
+                         c->xb.p, c->ctl, s));
+    HIP_TRY(launch_bnorm((const double*)B, ldb, n, (int)k, (double*)c->scal.p, s));
+    HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    double bnorm = 0.0;
+    HIP_TRY(hipMemcpyAsync(&bnorm, c->scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->h_ctl->stop == STOP_INVALID) {
+        const Ctl& h = *c->h_ctl;
+        jacobi_status vs;
+        if (h.bad_zero != INT64_MAX || h.bad_nonfinite != INT64_MAX) {
+            vs = h.bad_zero < h.bad_nonfinite ? JACOBI_ERR_ZERO_DIAGONAL
+                                              : JACOBI_ERR_NONFINITE_INPUT;
+            info->bad_index = std::min(h.bad_zero, h.bad_nonfinite);
+        } else {
+            vs = JACOBI_ERR_NONFINITE_INPUT;
+            info->bad_index = h.bad_rhs;
+        }
+        set_error("input validation failed at row %lld", (long long)info->bad_index);
+        return vs;
+    }
+    // A_lo = round(A), its diagonal, and the inner-solve launch shape.
+    HIP_TRY(launch_convert((const double*)A, lda, n, lo, c->alo.p, ld_lo, s));
+    HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
+    const LaunchCfg rcfg = residual_cfg(n, (int)k, c->num_cus);
+    const LaunchCfg icfg = default_cfg(lo, n, (int)k, c->num_cus);
+
+    void* xcur = c->xa.p;
+    void* xnext = c->xb.p;
+    const float* dlt = nullptr;  // correction to add in the next residual pass
+    int32_t inner_total = 0, outer = 0;
+    double rel = -1.0, last_delta = -1.0, kms = 0.0;
+    int64_t launches = 0;
+    jacobi_status result = JACOBI_NOT_CONVERGED;
+    for (;;) {
+        // Residual pass: x <- x + d, r = B - A x, ||r||_2 / ||B||_2.
+        HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
+        SweepArgs ra{};
+        ra.A = A;
+        ra.lda = lda;
+        ra.B = B;
+        ra.ldb = ldb;
+        ra.xin = xcur;
+        ra.xout = xnext;
+        ra.ldin = kp;
+        ra.ldout = kp;
+        ra.n = n;
+        ra.k = (int)k;
+        ra.kpad = kp;
+        ra.sweep = outer + 1;
+        ra.seq = 1;
+        ra.ctl = c->ctl;
+        ra.slots = c->slots;
+        ra.parts = c->parts;
+        ra.test = TEST_RESID;
+        ra.rel = o.refine_tol;
+        ra.bnorm = bnorm;
+        ra.aligned = (((uintptr_t)A % 16) == 0 && ((size_t)lda * 8) % 16 == 0) ? 1 : 0;
+        ra.dlt = dlt;
+        ra.r64 = (double*)c->r64.p;
+        ra.rlo = (float*)c->rlo.p;
+        HIP_TRY(launch_residual(ra, rcfg, s));
+        std::swap(xcur, xnext);
+        outer += 1;
+        HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        rel = bits_to_double(c->h_ctl->last_delta_bits);
+        if (c->h_ctl->stop == STOP_CONVERGED) {
+            result = JACOBI_OK;
+            break;
+        }
+        if (c->h_ctl->stop == STOP_DIVERGED) {
+            result = JACOBI_DIVERGED;
+            break;
+        }
+        if (outer > o.max_outer) {
+            result = JACOBI_NOT_CONVERGED;
+            break;
+        }
+        // Inner solve A_lo d = r from d = 0.
+        HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
+        HIP_TRY(launch_zero_rows(4, c->d0.p, kp, n, kp, s));
+        HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
+        SweepArgs ia{};
+        ia.A = c->alo.p;
+        ia.lda = ld_lo;
+        ia.B = c->rlo.p;
+        ia.ldb = kp;
+        ia.diag = c->diag_lo.p;
+        ia.n = n;
+        ia.k = (int)k;
+        ia.kpad = kp;
+        ia.ldin = kp;
+        ia.ldout = kp;
+        ia.ctl = c->ctl;
+        ia.slots = c->slots;
+        ia.parts = c->parts;
+        ia.test = TEST_REL;
+        ia.rel = o.inner_rel_tol;
+        ia.norm = JACOBI_NORM_INF;
+        ia.aligned = 1;
+        void* dbufs[2] = {c->d0.p, c->d1.p};
+        uint32_t stop = 0;
+        int32_t K = 0;
+        double xmax = 0.0;
+        jacobi_status st = run_sweeps(c, lo, ia, icfg, dbufs, o.max_inner, o.sync_every, o.profile,
+                                      s, &stop, &K, &last_delta, &xmax, &kms, &launches);
+        if (st != JACOBI_OK) return st;
+        inner_total += K;
+        if (stop == STOP_DIVERGED) {
+            result = JACOBI_DIVERGED;
+            break;
+        }
+        dlt = (const float*)dbufs[K & 1];
+    }
+    HIP_TRY(launch_copy_rows(8, xcur, kp, X, ldx, n, (int)k, s));
+    HIP_TRY(hipEventRecord(c->ev_end, s));
+    HIP_TRY(hipEventSynchronize(c->ev_end));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_begin, c->ev_end));
+    info->device_ms = ms;
+    info->iterations = inner_total;
+    info->outer_iterations = outer;
+    info->rel_residual = rel;
+    info->final_delta = last_delta;
+    info->sweep_kernel_ms = kms;
+    info->sweep_kernel_launches = launches;
+    info->bad_index = -1;
+    return result;
+}
+
+}  // namespace jac

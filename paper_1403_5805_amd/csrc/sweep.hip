@@ -1,0 +1,846 @@
+// Dense Jacobi sweep kernels for gfx950 (CDNA4, wave64).
+//
+// One launch performs one sweep of the component equation of sec. 2 of the
+// paper,  x_i^(k) = (beta_i - sum_{j != i} alpha_ij x_j^(k-1)) / alpha_ii,
+// for every row i and right-hand side c, fused with the distance
+// max|x^(k) - x^(k-1)| (or its Euclidean form, sec. 3.1) and the stop test of
+// the serial pseudocode (sec. 2, step (b)).
+//
+// Design (HBM-bound streaming, 0.5 flop/byte for one right-hand side in FP32):
+//   * A is streamed once per sweep with 16-byte non-temporal loads; every wave
+//     owns R consecutive rows and its 64 lanes cover 64*VEC consecutive columns
+//     per load, so each row segment is a contiguous 1 KiB read.
+//   * x^(k-1) is staged in LDS (the whole vector when it fits, else column
+//     chunks) and read back with 16-byte LDS loads; the R rows of a wave share
+//     each x read.
+//   * Each lane keeps R*K accumulators; a butterfly shuffle reduces them across
+//     the wave in a fixed order (results do not depend on timing).
+//   * The epilogue divides by alpha_ii (IEEE division), writes x^(k) into the
+//     other ping-pong buffer and folds |x^(k) - x^(k-1)| into a per-workgroup
+//     maximum, reduced across the grid with one atomic max per workgroup on
+//     the bit pattern of the non-negative double (a NaN compares above +Inf,
+//     so a NaN distance is never lost).
+//   * The last workgroup to finish (atomic ticket) takes the stop decision and
+//     writes a device stop flag; later sweep launches see it and return at once,
+//     so the host only checks the flag every few sweeps.
+//   * The same kernel, in residual mode, computes r = b - A x in FP64 (no
+//     diagonal mask, no division) for iterative refinement, with the update
+//     x += d fused into the staging of x.
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace jac {
+
+typedef uint16_t bf16_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Elem;
+template <>
+struct Elem<double> {
+    static constexpr int vec = 2;
+};
+template <>
+struct Elem<float> {
+    static constexpr int vec = 4;
+};
+template <>
+struct Elem<bf16_t> {
+    static constexpr int vec = 8;
+};
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+template <typename TA, typename TX>
+__device__ __forceinline__ TX widen(TA a);
+template <>
+__device__ __forceinline__ double widen<double, double>(double a) {
+    return a;
+}
+template <>
+__device__ __forceinline__ float widen<float, float>(float a) {
+    return a;
+}
+template <>
+__device__ __forceinline__ float widen<bf16_t, float>(bf16_t a) {
+    return bf16_bits_to_f32(a);
+}
+
+// Unpack one 16-byte vector of TA into VEC values of TX.
+template <typename TA, typename TX>
+__device__ __forceinline__ void unpack16(const u32x4& v, TX* out);
+template <>
+__device__ __forceinline__ void unpack16<double, double>(const u32x4& v, double* out) {
+    out[0] = __hiloint2double((int)v.y, (int)v.x);
+    out[1] = __hiloint2double((int)v.w, (int)v.z);
+}
+template <>
+__device__ __forceinline__ void unpack16<float, float>(const u32x4& v, float* out) {
+    out[0] = __uint_as_float(v.x);
+    out[1] = __uint_as_float(v.y);
+    out[2] = __uint_as_float(v.z);
+    out[3] = __uint_as_float(v.w);
+}
+template <>
+__device__ __forceinline__ void unpack16<bf16_t, float>(const u32x4& v, float* out) {
+    out[0] = bf16_bits_to_f32(v.x & 0xffffu);
+    out[1] = bf16_bits_to_f32(v.x >> 16);
+    out[2] = bf16_bits_to_f32(v.y & 0xffffu);
+    out[3] = bf16_bits_to_f32(v.y >> 16);
+    out[4] = bf16_bits_to_f32(v.z & 0xffffu);
+    out[5] = bf16_bits_to_f32(v.z >> 16);
+    out[6] = bf16_bits_to_f32(v.w & 0xffffu);
+    out[7] = bf16_bits_to_f32(v.w >> 16);
+}
+
+__device__ __forceinline__ double tx_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tx_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint64_t o = __shfl_xor(v, m, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t ld_stop(const Ctl* c) {
+    return __hip_atomic_load(&c->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Control-block initialisation.  full = 1 also clears the validation fields.
+__global__ void k_init_ctl(Ctl* ctl, Slot* slots, int full) {
+    if (threadIdx.x == 0) {
+        ctl->stop = STOP_RUNNING;
+        ctl->stop_sweep = 0;
+        ctl->sweeps_done = 0;
+        ctl->last_delta_bits = dbits(-1.0);
+        ctl->last_xmax_bits = 0;
+        if (full) {
+            ctl->bad_zero = INT64_MAX;
+            ctl->bad_nonfinite = INT64_MAX;
+            ctl->bad_rhs = INT64_MAX;
+            ctl->setup_ticket = 0;
+        }
+        for (int s = 0; s < 2; ++s) {
+            slots[s].dmax_bits = 0;
+            slots[s].xmax_bits = 0;
+            slots[s].ticket = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Setup (validation + initial iterate).  Gathers alpha_ii into diag, records
+// the first row with a zero or non-finite diagonal (sec. 2: the method fails
+// when alpha_ii = 0) and the first row with a non-finite B or X0 entry, copies
+// X0 (or zeros) into the iterate buffer w0 (leading dim kpad, padding columns
+// zero) and clears w1.  The last workgroup raises STOP_INVALID if anything was
+// wrong, so no sweep runs and X is never written.
+template <typename TA, typename TX>
+__global__ void k_setup(const TA* __restrict__ A, int64_t lda, const TX* __restrict__ B,
+                        int64_t ldb, const TX* __restrict__ X0, int64_t ldx0, int64_t n, int k,
+                        int kpad, TX* __restrict__ diag, TX* __restrict__ w0, TX* __restrict__ w1,
+                        Ctl* ctl) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const TX d = widen<TA, TX>(A[i * lda + i]);
+        diag[i] = d;
+        if (d == (TX)0)
+            __hip_atomic_fetch_min(&ctl->bad_zero, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (!isfinite(d))
+            __hip_atomic_fetch_min(&ctl->bad_nonfinite, i, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        bool bad = false;
+        for (int c = 0; c < kpad; ++c) {
+            TX x0 = (TX)0;
+            if (c < k) {
+                if (X0) x0 = X0[i * ldx0 + c];
+                const TX b = B[i * ldb + c];
+                if (!isfinite(b) || !isfinite(x0)) bad = true;
+            }
+            w0[i * kpad + c] = x0;
+            w1[i * kpad + c] = (TX)0;
+        }
+        if (bad)
+            __hip_atomic_fetch_min(&ctl->bad_rhs, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = __hip_atomic_fetch_add(&ctl->setup_ticket, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (t == gridDim.x - 1) {
+            __threadfence();
+            const int64_t bz = __hip_atomic_load(&ctl->bad_zero, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t bn = __hip_atomic_load(&ctl->bad_nonfinite, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t br = __hip_atomic_load(&ctl->bad_rhs, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (bz != INT64_MAX || bn != INT64_MAX || br != INT64_MAX)
+                __hip_atomic_store(&ctl->stop, (uint32_t)STOP_INVALID, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage columns [c0, c0 + cl) of the iterate (leading dim KT, contiguous rows)
+// into LDS.  In residual mode (dlt != null) the staged value is x + d, the
+// refinement update, formed in FP64.
+template <typename TX, int KT, int NT>
+__device__ __forceinline__ void stage_x(TX* __restrict__ xs, const TX* __restrict__ xin,
+                                        const float* __restrict__ dlt, int64_t c0, int64_t cl) {
+    const int tid = threadIdx.x;
+    const int64_t elems = cl * KT;
+    const TX* src = xin + c0 * KT;
+    if (dlt == nullptr) {
+        const int64_t nvec = (elems * (int64_t)sizeof(TX)) / 16;
+        const u32x4* s16 = reinterpret_cast<const u32x4*>(src);
+        u32x4* d16 = reinterpret_cast<u32x4*>(xs);
+        for (int64_t base = 0; base < nvec; base += (int64_t)NT * 8) {
+            u32x4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t idx = base + (int64_t)u * NT + tid;
+                if (idx < nvec) v[u] = s16[idx];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t idx = base + (int64_t)u * NT + tid;
+                if (idx < nvec) d16[idx] = v[u];
+            }
+        }
+        for (int64_t e = nvec * 16 / (int64_t)sizeof(TX) + tid; e < elems; e += NT) xs[e] = src[e];
+    } else {
+        const float* ds = dlt + c0 * KT;
+        for (int64_t base = 0; base < elems; base += (int64_t)NT * 4) {
+            TX v[4];
+            float w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t idx = base + (int64_t)u * NT + tid;
+                if (idx < elems) {
+                    v[u] = src[idx];
+                    w[u] = ds[idx];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t idx = base + (int64_t)u * NT + tid;
+                if (idx < elems) xs[idx] = v[u] + (TX)w[u];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Accumulate sum_j alpha_ij x_j over columns [c0, c0 + cl) for the R rows
+// i0..i0+R-1 of this wave.  MODE 0 skips j == i (sec. 2: the sum runs over
+// j != i); MODE 1 (residual) keeps every term.
+template <typename TA, typename TX, int KT, int R, int MODE>
+__device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restrict__ A, int64_t lda,
+                                           int64_t n, int64_t i0, int64_t c0, int64_t cl,
+                                           const TX* __restrict__ xs, int lane, bool aligned) {
+    constexpr int VEC = Elem<TA>::vec;
+    constexpr int SPAN = 64 * VEC;
+    constexpr int U = (R * KT * (int)sizeof(TX) <= 32) ? 2 : 1;
+    constexpr int NV = (VEC * KT * (int)sizeof(TX)) / 16;  // LDS 16-byte reads per column group
+    static_assert(NV >= 1, "x slice must be at least 16 bytes");
+    const TA* rowp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = (i0 + r < n) ? (i0 + r) : (n - 1);
+        rowp[r] = A + i * lda + c0;
+    }
+    const int64_t nfull = aligned ? (cl / SPAN) : 0;
+    const int64_t dlo = i0 - c0;  // diagonal of row i0+r sits at relative column dlo+r
+    int64_t it = 0;
+    for (; it + U <= nfull; it += U) {
+        u32x4 v[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[u][r] = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x4*>(rowp[r] + (it + u) * SPAN + lane * VEC));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t cbase = (it + u) * SPAN;
+            const int64_t col = cbase + (int64_t)lane * VEC;
+            TX xv[VEC * KT];
+            {
+                u32x4 t[NV];
+                const u32x4* src = reinterpret_cast<const u32x4*>(xs + col * KT);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) t[q] = src[q];
+                __builtin_memcpy(xv, t, sizeof(xv));
+            }
+            TX a[R][VEC];
+#pragma unroll
+            for (int r = 0; r < R; ++r) unpack16<TA, TX>(v[u][r], a[r]);
+            if (MODE == 0 && cbase < dlo + R && dlo < cbase + SPAN) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (col + e == dlo + r) a[r][e] = (TX)0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                    for (int c = 0; c < KT; ++c)
+                        acc[r][c] = tx_fma(a[r][e], xv[e * KT + c], acc[r][c]);
+        }
+    }
+    for (; it < nfull; ++it) {
+        u32x4 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4*>(rowp[r] + it * SPAN + lane * VEC));
+        const int64_t cbase = it * SPAN;
+        const int64_t col = cbase + (int64_t)lane * VEC;
+        TX xv[VEC * KT];
+        {
+            u32x4 t[NV];
+            const u32x4* src = reinterpret_cast<const u32x4*>(xs + col * KT);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) t[q] = src[q];
+            __builtin_memcpy(xv, t, sizeof(xv));
+        }
+        TX a[R][VEC];
+#pragma unroll
+        for (int r = 0; r < R; ++r) unpack16<TA, TX>(v[r], a[r]);
+        if (MODE == 0 && cbase < dlo + R && dlo < cbase + SPAN) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (col + e == dlo + r) a[r][e] = (TX)0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                for (int c = 0; c < KT; ++c) acc[r][c] = tx_fma(a[r][e], xv[e * KT + c], acc[r][c]);
+    }
+    // Ragged tail (and the whole row when rows are not 16-byte aligned).
+    for (int64_t col = nfull * SPAN + lane; col < cl; col += 64) {
+        TX xv[KT];
+#pragma unroll
+        for (int c = 0; c < KT; ++c) xv[c] = xs[col * KT + c];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            TX a = widen<TA, TX>(rowp[r][col]);
+            if (MODE == 0 && col == dlo + r) a = (TX)0;
+#pragma unroll
+            for (int c = 0; c < KT; ++c) acc[r][c] = tx_fma(a, xv[c], acc[r][c]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid-wide reduction of the per-lane distance statistics and the stop
+// decision by the last workgroup.  All threads of the workgroup must call it.
+template <int W>
+__device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax, uint64_t xmax,
+                                              double sq) {
+    __shared__ uint64_t red_d[W], red_m[W];
+    __shared__ double red_s[W];
+    __shared__ uint32_t s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool need_sum = (p.norm == 1) || (p.test == TEST_RESID);
+    dmax = wave_max_u64(dmax);
+    xmax = wave_max_u64(xmax);
+    sq = wave_sum(sq);
+    if (lane == 0) {
+        red_d[wave] = dmax;
+        red_m[wave] = xmax;
+        red_s[wave] = sq;
+    }
+    __syncthreads();
+    const int total = gridDim.x * gridDim.y;
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    Slot* sl = &p.slots[p.seq & 1];
+    double* parts = p.parts + (size_t)(p.seq & 1) * kMaxParts;
+    if (tid == 0) {
+        uint64_t D = 0, M = 0;
+        double S = 0.0;
+        for (int w = 0; w < W; ++w) {
+            D = red_d[w] > D ? red_d[w] : D;
+            M = red_m[w] > M ? red_m[w] : M;
+            S += red_s[w];
+        }
+        if (need_sum)
+            __hip_atomic_store(&parts[bid], S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&sl->xmax_bits, M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const uint32_t t =
+            __hip_atomic_fetch_add(&sl->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == (uint32_t)(total - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // This is the last workgroup: every other one has published its share.
+    double S = 0.0;
+    if (need_sum) {
+        for (int b = tid; b < total; b += W * 64)
+            S += __hip_atomic_load(&parts[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S = wave_sum(S);
+        __syncthreads();
+        if (lane == 0) red_s[wave] = S;
+        __syncthreads();
+        S = 0.0;
+        for (int w = 0; w < W; ++w) S += red_s[w];
+    }
+    if (tid == 0) {
+        const double dm =
+            bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double xm =
+            bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        uint32_t st = STOP_RUNNING;
+        double delta;
+        if (p.test == TEST_RESID) {
+            const double rn = sqrt(S);
+            delta = p.bnorm > 0.0 ? rn / p.bnorm : rn;
+            if (!isfinite(delta))
+                st = STOP_DIVERGED;
+            else if (S == 0.0 || delta < p.rel)
+                st = STOP_CONVERGED;
+        } else {
+            delta = (p.norm == 1) ? sqrt(S) : dm;
+            if (!isfinite(delta))
+                st = STOP_DIVERGED;
+            else if (p.test == TEST_ABS ? (delta < p.tol) : (delta <= p.rel * xm))
+                st = STOP_CONVERGED;
+        }
+        Ctl* c = p.ctl;
+        __hip_atomic_store(&c->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c->sweeps_done, p.sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (st != STOP_RUNNING) {
+            __hip_atomic_store(&c->stop_sweep, p.sweep, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->stop, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Clear the other slot for the next launch of this phase.
+        Slot* o = &p.slots[(p.seq + 1) & 1];
+        __hip_atomic_store(&o->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&o->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&o->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The sweep (MODE 0) / residual (MODE 1) kernel.
+//   grid.x : row blocks of W*R rows (grid-stride when fewer workgroups)
+//   grid.y : column groups of KT right-hand sides (k > 32 only)
+template <typename TA, typename TX, int KT, int R, int W, int MODE>
+__global__ __launch_bounds__(W * 64, (R * KT * sizeof(TX) <= 64) ? 4 : 2) void k_sweep(SweepArgs p) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    TX* xs = reinterpret_cast<TX*>(lds_raw);
+    if (ld_stop(p.ctl) != STOP_RUNNING) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = p.n;
+    const int kp = p.kpad;
+    const int cb = blockIdx.y * KT;
+    const int kc = (p.k - cb) < KT ? (p.k - cb) : KT;
+    const TA* A = reinterpret_cast<const TA*>(p.A);
+    const TX* B = reinterpret_cast<const TX*>(p.B);
+    const TX* xin = reinterpret_cast<const TX*>(p.xin);
+    const TX* diag = reinterpret_cast<const TX*>(p.diag);
+    const bool aligned = p.aligned != 0;
+    // Column groups (k > KT) stage a strided slice; for one group the iterate
+    // rows are contiguous with leading dim KT.
+    const TX* xsrc = xin + cb;
+    const float* dsrc = (MODE == 1 && p.dlt) ? (p.dlt + cb) : nullptr;
+
+    uint64_t dmax = 0, xmax = 0;
+    double sq = 0.0;
+    const bool single = p.chunk >= n;
+    const bool contiguous = (kp == KT);
+
+    auto stage = [&](int64_t c0, int64_t cl) {
+        if (contiguous) {
+            stage_x<TX, KT, W * 64>(xs, xsrc, dsrc, c0, cl);
+        } else {
+            for (int64_t e = tid; e < cl * KT; e += W * 64) {
+                const int64_t j = c0 + e / KT;
+                const int c = (int)(e % KT);
+                TX v = (TX)0;
+                if (c < kc) {
+                    v = xsrc[j * kp + c];
+                    if (dsrc) v += (TX)dsrc[j * kp + c];
+                }
+                xs[e] = v;
+            }
+        }
+    };
+
+    if (single) {
+        stage(0, n);
+        __syncthreads();
+    }
+    const int64_t rpb = (int64_t)W * R;
+    for (int64_t rb = (int64_t)blockIdx.x * rpb; rb < n; rb += (int64_t)gridDim.x * rpb) {
+        const int64_t i0 = rb + (int64_t)wave * R;
+        TX acc[R][KT];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < KT; ++c) acc[r][c] = (TX)0;
+        for (int64_t c0 = 0; c0 < n; c0 += p.chunk) {
+            const int64_t cl = (n - c0) < p.chunk ? (n - c0) : p.chunk;
+            if (!single) {
+                __syncthreads();
+                stage(c0, cl);
+                __syncthreads();
+            }
+            if (i0 < n) accumulate<TA, TX, KT, R, MODE>(acc, A, p.lda, n, i0, c0, cl, xs, lane, aligned);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < KT; ++c) acc[r][c] = wave_sum(acc[r][c]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int c = 0; c < KT; ++c) {
+                const int t = r * KT + c;
+                const int64_t i = i0 + r;
+                if ((t & 63) == lane && i < n && c < kc) {
+                    const TX s = acc[r][c];
+                    if (MODE == 0) {
+                        const TX b = B[i * p.ldb + cb + c];
+                        const TX xn = (b - s) / diag[i];
+                        const TX xo = xin[i * kp + cb + c];
+                        reinterpret_cast<TX*>(p.xout)[i * kp + cb + c] = xn;
+                        const double dd = fabs((double)xn - (double)xo);
+                        const double am = fabs((double)xn);
+                        const uint64_t db = dbits(dd), mb = dbits(am);
+                        dmax = db > dmax ? db : dmax;
+                        xmax = mb > xmax ? mb : xmax;
+                        sq += dd * dd;
+                    } else {
+                        // residual r = b - A x with x already updated in LDS;
+                        // the owner of row i also stores the updated x.
+                        const double b = (double)B[i * p.ldb + cb + c];
+                        const double rr = b - (double)s;
+                        p.r64[i * kp + cb + c] = rr;
+                        p.rlo[i * kp + cb + c] = (float)rr;
+                        double xnew = (double)xin[i * kp + cb + c];
+                        if (dsrc) xnew += (double)dsrc[i * kp + c];
+                        reinterpret_cast<double*>(p.xout)[i * kp + cb + c] = xnew;
+                        sq += rr * rr;
+                        const uint64_t mb = dbits(fabs(rr));
+                        dmax = mb > dmax ? mb : dmax;
+                    }
+                }
+            }
+        }
+    }
+    finish_launch<W>(p, dmax, xmax, sq);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 -> FP32 / BF16 conversion of A (round to nearest, ties to even).
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
+    if (isnan(x)) return (uint16_t)0x7fc0u;
+    const double ax = fabs(x);
+    const uint32_t sign = (x < 0.0 || (x == 0.0 && signbit(x))) ? 0x8000u : 0u;
+    double r;
+    if (ax < 0x1.0p-126) {
+        // subnormal bf16 range: the quantum is 2^-133
+        r = __builtin_rint(ax * 0x1.0p133) * 0x1.0p-133;
+    } else {
+        // keep 8 significant bits of the double (7 explicit): round at bit 45
+        uint64_t u = (uint64_t)__double_as_longlong(ax);
+        const uint64_t lsb = (u >> 45) & 1u;
+        u += (((uint64_t)1 << 44) - 1) + lsb;
+        u &= ~(((uint64_t)1 << 45) - 1);
+        r = __longlong_as_double((long long)u);
+    }
+    // r is exactly a bf16 magnitude (or >= 2^128 -> overflow to inf)
+    uint32_t fb;
+    if (r >= 0x1.0p128)
+        fb = 0x7f800000u;
+    else
+        fb = __float_as_uint((float)r);
+    return (uint16_t)(sign | (fb >> 16));
+}
+
+__global__ void k_convert_f32(const double* __restrict__ A, int64_t lda, int64_t n,
+                              float* __restrict__ out, int64_t ldo) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) out[i * ldo + j] = (float)A[i * lda + j];
+}
+
+__global__ void k_convert_bf16(const double* __restrict__ A, int64_t lda, int64_t n,
+                               uint16_t* __restrict__ out, int64_t ldo) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+            out[i * ldo + j] = f64_to_bf16_rne(A[i * lda + j]);
+}
+
+// alpha_ii of a reduced-precision copy of A, widened to float.
+template <typename TA>
+__global__ void k_gather_diag(const TA* __restrict__ A, int64_t lda, int64_t n, float* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = widen<TA, float>(A[i * lda + i]);
+}
+
+// ||B||_2 over all n*k entries, one workgroup, fixed summation order.
+__global__ void k_bnorm(const double* __restrict__ B, int64_t ldb, int64_t n, int k, double* out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        for (int c = 0; c < k; ++c) {
+            const double v = B[i * ldb + c];
+            s += v * v;
+        }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) S += red[w];
+        *out = sqrt(S);
+    }
+}
+
+template <typename T>
+__global__ void k_copy_rows(const T* __restrict__ src, int64_t lds, T* __restrict__ dst,
+                            int64_t ldd, int64_t n, int k) {
+    // one thread per (row, column); k is small, rows spread over the grid
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        for (int c = 0; c < k; ++c) dst[i * ldd + c] = src ? src[i * lds + c] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static int blocks_for(int64_t work, int threads, int cap) {
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_init_ctl(Ctl* ctl, Slot* slots, int full, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, ctl, slots, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(int32_t a_dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        const void* X0, int64_t ldx0, int64_t n, int32_t k, int32_t kpad,
+                        void* diag, void* w0, void* w1, Ctl* ctl, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = blocks_for(n, threads, 1024);
+    switch (a_dtype) {
+        case 0:
+            hipLaunchKernelGGL((k_setup<double, double>), dim3(blocks), dim3(threads), 0, s,
+                               (const double*)A, lda, (const double*)B, ldb, (const double*)X0,
+                               ldx0, n, k, kpad, (double*)diag, (double*)w0, (double*)w1, ctl);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_setup<float, float>), dim3(blocks), dim3(threads), 0, s,
+                               (const float*)A, lda, (const float*)B, ldb, (const float*)X0, ldx0,
+                               n, k, kpad, (float*)diag, (float*)w0, (float*)w1, ctl);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_setup<bf16_t, float>), dim3(blocks), dim3(threads), 0, s,
+                               (const bf16_t*)A, lda, (const float*)B, ldb, (const float*)X0,
+                               ldx0, n, k, kpad, (float*)diag, (float*)w0, (float*)w1, ctl);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TA, typename TX, int KT, int R, int W, int MODE>
+static hipError_t launch_one(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
+    if constexpr (R * KT * sizeof(TX) > 256) {
+        return hipErrorInvalidValue;
+    } else {
+        const int gy = (a.k + KT - 1) / KT;
+        const size_t lds = (size_t)a.chunk * KT * sizeof(TX);
+        hipLaunchKernelGGL((k_sweep<TA, TX, KT, R, W, MODE>), dim3(cfg.grid, gy), dim3(W * 64),
+                           lds, s, a);
+        return hipGetLastError();
+    }
+}
+
+template <typename TA, typename TX, int KT, int MODE>
+static hipError_t launch_rw(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
+    if (cfg.waves == 8) {
+        if (cfg.rows == 4) return launch_one<TA, TX, KT, 4, 8, MODE>(a, cfg, s);
+        if (cfg.rows == 2) return launch_one<TA, TX, KT, 2, 8, MODE>(a, cfg, s);
+        if (cfg.rows == 1) return launch_one<TA, TX, KT, 1, 8, MODE>(a, cfg, s);
+    } else if (cfg.waves == 4) {
+        if (cfg.rows == 4) return launch_one<TA, TX, KT, 4, 4, MODE>(a, cfg, s);
+        if (cfg.rows == 2) return launch_one<TA, TX, KT, 2, 4, MODE>(a, cfg, s);
+        if (cfg.rows == 1) return launch_one<TA, TX, KT, 1, 4, MODE>(a, cfg, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int kt_for(int k) {
+    int kt = 1;
+    while (kt < k && kt < 32) kt <<= 1;
+    return kt;
+}
+
+template <typename TA, typename TX, int MODE>
+static hipError_t launch_kt(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
+    switch (kt_for(a.k)) {
+        case 1: return launch_rw<TA, TX, 1, MODE>(a, cfg, s);
+        case 2: return launch_rw<TA, TX, 2, MODE>(a, cfg, s);
+        case 4: return launch_rw<TA, TX, 4, MODE>(a, cfg, s);
+        case 8: return launch_rw<TA, TX, 8, MODE>(a, cfg, s);
+        case 16: return launch_rw<TA, TX, 16, MODE>(a, cfg, s);
+        case 32: return launch_rw<TA, TX, 32, MODE>(a, cfg, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cfg,
+                        hipStream_t s) {
+    SweepArgs p = a;
+    p.chunk = cfg.chunk;
+    switch (a_dtype) {
+        case 0: return launch_kt<double, double, 0>(p, cfg, s);
+        case 1: return launch_kt<float, float, 0>(p, cfg, s);
+        case 2: return launch_kt<bf16_t, float, 0>(p, cfg, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
+    SweepArgs p = a;
+    p.chunk = cfg.chunk;
+    return launch_kt<double, double, 1>(p, cfg, s);
+}
+
+hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
+                          int64_t ldo, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = (int)(n < 16384 ? n : 16384);
+    if (to_dtype == 1)
+        hipLaunchKernelGGL(k_convert_f32, dim3(blocks), dim3(threads), 0, s, A, lda, n,
+                           (float*)out, ldo);
+    else if (to_dtype == 2)
+        hipLaunchKernelGGL(k_convert_bf16, dim3(blocks), dim3(threads), 0, s, A, lda, n,
+                           (uint16_t*)out, ldo);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64_t n,
+                              void* out, hipStream_t s) {
+    const int blocks = blocks_for(n, 256, 1024);
+    if (a_dtype == 1)
+        hipLaunchKernelGGL((k_gather_diag<float>), dim3(blocks), dim3(256), 0, s, (const float*)A,
+                           lda, n, (float*)out);
+    else if (a_dtype == 2)
+        hipLaunchKernelGGL((k_gather_diag<bf16_t>), dim3(blocks), dim3(256), 0, s,
+                           (const bf16_t*)A, lda, n, (float*)out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_bnorm(const double* B, int64_t ldb, int64_t n, int32_t k, double* out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_bnorm, dim3(1), dim3(1024), 0, s, B, ldb, n, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(int32_t elem_bytes, const void* src, int64_t lds, void* dst,
+                            int64_t ldd, int64_t n, int32_t k, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = blocks_for(n, threads, 4096);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL((k_copy_rows<double>), dim3(blocks), dim3(threads), 0, s,
+                           (const double*)src, lds, (double*)dst, ldd, n, k);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL((k_copy_rows<float>), dim3(blocks), dim3(threads), 0, s,
+                           (const float*)src, lds, (float*)dst, ldd, n, k);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t n, int32_t k,
+                            hipStream_t s) {
+    return launch_copy_rows(elem_bytes, nullptr, 0, dst, ldd, n, k, s);
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape heuristics.
+
+static int64_t span_of(int32_t a_dtype) { return a_dtype == 0 ? 128 : (a_dtype == 1 ? 256 : 512); }
+
+LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus) {
+    LaunchCfg c;
+    const int kt = kt_for(k);
+    const int sx = (a_dtype == 0) ? 8 : 4;
+    c.waves = 8;
+    int r = 256 / (kt * sx);
+    c.rows = r >= 4 ? 4 : (r >= 2 ? 2 : 1);
+    // Prefer more workgroups over more rows per wave when the system is small.
+    while (c.rows > 1 && (n + (int64_t)c.waves * c.rows - 1) / ((int64_t)c.waves * c.rows) <
+                             2 * (int64_t)num_cus)
+        c.rows >>= 1;
+    if ((n + (int64_t)c.waves * c.rows - 1) / ((int64_t)c.waves * c.rows) < 2 * (int64_t)num_cus)
+        c.waves = 4;
+    const int64_t span = span_of(a_dtype);
+    int64_t cap = 65536 / ((int64_t)kt * sx);
+    cap = (cap / span) * span;
+    if (cap < span) cap = span;
+    c.chunk = n <= cap ? n : cap;
+    const int64_t rpb = (int64_t)c.waves * c.rows;
+    int64_t nb = (n + rpb - 1) / rpb;
+    int64_t gcap = (int64_t)num_cus * 8;
+    const int64_t gy = (k + 31) / 32;
+    if (gcap * gy > kMaxParts) gcap = kMaxParts / gy;
+    c.grid = (int)(nb < gcap ? nb : gcap);
+    return c;
+}
+
+LaunchCfg residual_cfg(int64_t n, int32_t k, int num_cus) { return default_cfg(0, n, k, num_cus); }
+
+size_t sweep_lds_bytes(int32_t a_dtype, int32_t k, const LaunchCfg& cfg) {
+    const int sx = (a_dtype == 0) ? 8 : 4;
+    return (size_t)cfg.chunk * kt_for(k) * sx;
+}
+
+}  // namespace jac
