@@ -90,7 +90,8 @@ typedef struct {
     double inner_rel_tol;   /* REFINE: inner relative stop (default 1e-3)                 */
     int32_t max_inner;      /* REFINE: inner sweep cap per correction (default 200)       */
     int32_t max_outer;      /* REFINE: correction cap (default 50)                        */
-    double refine_tol;      /* REFINE: ||r||_2 / ||B||_2 target (default 1e-10)           */
+    double refine_tol;      /* REFINE: ||r||_2 / ||B||_2 target (default 1e-11, so that the
+                               forward error meets 1e-10 for moderately conditioned A)   */
     int32_t sync_every;     /* sweeps between host checks of the stop flag, 0 = adaptive  */
     int32_t profile;        /* 1: time every sweep kernel with HIP events (see info)      */
 } jacobi_options;
@@ -145,6 +146,36 @@ jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k, int32_t a_dtyp
                            const void* A, int64_t lda, const void* B, int64_t ldb,
                            const void* X0, void* X, int64_t ldx, const jacobi_options* opt,
                            hipStream_t stream, jacobi_info* info);
+
+/* One system of a batch (device pointers; same conventions as jacobi_solve). */
+typedef struct {
+    int64_t n, k;       /* size and right-hand sides (batched FP32/BF16: k <= 32)  */
+    const void* A;      /* n x n, leading dimension lda                            */
+    int64_t lda;
+    const void* B;      /* n x k, leading dimension ldb                            */
+    int64_t ldb;
+    const void* X0;     /* n x k initial approximation (ldx), NULL => zero         */
+    void* X;            /* n x k output, leading dimension ldx                     */
+    int64_t ldx;
+} jacobi_system;
+
+/* Solve `count` independent systems (sec. 2 iteration on each) with one
+ * persistent launch.  a_dtype F32 or BF16: A as given, B/X0/X float, every
+ * system k <= 32; the sweeps run on MFMA tiles, large systems are split over
+ * several workgroups that meet at a per-system device barrier after each
+ * sweep, small systems are owned by one workgroup and packed.  Every system
+ * stops on its own (opt->tol / opt->max_iter, PLAIN mode only, INF or L2
+ * distance over its n*k entries).  a_dtype F64 runs the systems one after the
+ * other through the plain path.
+ *
+ * systems, infos: host arrays of `count` entries.  Returns JACOBI_OK when the
+ * launch ran (per-system outcomes in infos[i].status; a system with bad
+ * arguments gets JACOBI_ERR_INVALID_ARG and is skipped), or an error for the
+ * whole call (bad options, device failure).  Results depend only on each
+ * system's own data: a system gives bitwise the same X alone and in a batch. */
+jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count, const jacobi_system* systems,
+                                   int32_t a_dtype, const jacobi_options* opt, hipStream_t stream,
+                                   jacobi_info* infos);
 
 /* Human-readable name of a status code (static string). */
 const char* jacobi_status_string(int32_t status);

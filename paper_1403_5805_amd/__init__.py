@@ -20,7 +20,7 @@ from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVA
                    ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
                    F64, NOT_CONVERGED, OK, PENDING, Info, Options)
 
-__all__ = ["solve", "status_string", "last_error", "Context",
+__all__ = ["solve", "solve_batched", "status_string", "last_error", "Context",
            "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
            "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
            "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
@@ -66,7 +66,7 @@ def _ld(t) -> int:
 
 
 def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype="bf16",
-                 inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-10,
+                 inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-11,
                  sync_every=0, profile=False) -> Options:
     o = Options()
     _lib.load().jacobi_options_default(ctypes.byref(o))
@@ -157,3 +157,5 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
             raise RuntimeError(f"jacobi_solve failed: {d['status_name']}: {d['error']}")
     return out, d
 
+
+from .batched import solve_batched  # noqa: E402

@@ -1,0 +1,63 @@
+"""Batched solves: many independent systems in one persistent launch
+(jacobi_solve_batched).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+
+def solve_batched(systems, *, outs=None, ctx=None, stream=None, tol=1e-8, max_iter=10000,
+                  norm="inf"):
+    """Solve each (A, B) or (A, B, x0) in `systems` on the GPU.
+
+    All A share one dtype: float32 or bfloat16 (B, x0 float32, k <= 32; one
+    persistent MFMA launch), or float64 (systems solved one after another).
+    Returns (list of X, list of info dicts)."""
+    import torch
+
+    from . import _a_dtype, _ld, _stream_handle, make_options, status_string
+    lib = _lib.load()
+    count = len(systems)
+    if count == 0:
+        return [], []
+    dt = _a_dtype(systems[0][0])
+    arr = (_lib.System * count)()
+    xs = []
+    keep = []
+    for i, sysd in enumerate(systems):
+        A, B = sysd[0], sysd[1]
+        x0 = sysd[2] if len(sysd) > 2 else None
+        if _a_dtype(A) != dt:
+            raise TypeError("all systems of a batch share A's dtype")
+        vec = B.dim() == 1
+        n = A.shape[0]
+        k = 1 if vec else B.shape[1]
+        X = outs[i] if outs is not None else torch.empty_like(B)
+        if x0 is not None and _ld(x0) != _ld(X):
+            x0 = x0.contiguous()
+        keep.append(x0)
+        arr[i].n = n
+        arr[i].k = k
+        arr[i].A = A.data_ptr()
+        arr[i].lda = _ld(A)
+        arr[i].B = B.data_ptr()
+        arr[i].ldb = 1 if vec else _ld(B)
+        arr[i].X0 = x0.data_ptr() if x0 is not None else None
+        arr[i].X = X.data_ptr()
+        arr[i].ldx = 1 if vec else _ld(X)
+        xs.append(X)
+    o = make_options(tol=tol, max_iter=max_iter, norm=norm)
+    infos = (_lib.Info * count)()
+    dev = systems[0][0].device
+    st = lib.jacobi_solve_batched(ctx.handle if ctx else None, count, arr, dt, ctypes.byref(o),
+                                  _stream_handle(stream, dev), infos)
+    if st != 0:
+        raise RuntimeError(f"jacobi_solve_batched: {status_string(st)}: "
+                           f"{lib.jacobi_last_error().decode()}")
+    out = []
+    for i in range(count):
+        d = infos[i].as_dict()
+        d["status_name"] = status_string(d["status"])
+        out.append(d)
+    return xs, out

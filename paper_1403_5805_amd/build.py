@@ -25,8 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 
-SOURCES = ["sweep.hip", "mfma.hip", "batched.hip", "api.cpp", "refine.cpp", "batch_api.cpp",
-           "serve.cpp"]
+SOURCES = ["sweep.hip", "batched.hip", "api.cpp", "refine.cpp", "batch_api.cpp", "serve.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/jacobi.h"
+#include "batch.h"
 #include "ctx.h"
 #include "internal.h"
 
@@ -74,7 +75,7 @@ jacobi_status ctx_init(jacobi_ctx* c, int device) {
 void ctx_release(jacobi_ctx* c) {
     hipSetDevice(c->device);
     for (DevBuf* b : {&c->diag, &c->w0, &c->w1, &c->alo, &c->diag_lo, &c->xa, &c->xb, &c->r64,
-                      &c->rlo, &c->d0, &c->d1, &c->scal})
+                      &c->rlo, &c->d0, &c->d1, &c->scal, &c->bws, &c->bmeta})
         b->release();
     if (c->ctl) hipFree(c->ctl);
     if (c->slots) hipFree(c->slots);
@@ -249,10 +250,20 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
     return JACOBI_OK;
 }
 
-static jacobi_status solve_plain(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_dtype,
+jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_dtype,
                                  const void* A, int64_t lda, const void* B, int64_t ldb,
                                  const void* X0, void* X, int64_t ldx, const jacobi_options& o,
                                  hipStream_t s, jacobi_info* info) {
+    // Several right-hand sides in FP32 / BF16: the sweep is a real dense
+    // contraction, run on MFMA tiles by the persistent kernel.
+    if (a_dtype != JACOBI_F64 && k >= 8 && k <= 32 && o.profile == 0) {
+        BatchItem it{n, k, A, lda, B, ldb, X0, X, ldx, o.max_iter};
+        jacobi_status st = run_batched(c, 1, &it, a_dtype, o, TEST_ABS, 0.0, s, info);
+        if (st != JACOBI_OK) return st;
+        if (info->status < 0 && info->status != JACOBI_ERR_INTERNAL)
+            set_error("input validation failed at row %lld", (long long)info->bad_index);
+        return (jacobi_status)info->status;
+    }
     const int kp = kpad_for(k);
     const size_t sx = a_dtype == JACOBI_F64 ? 8 : 4;
     HIP_TRY(c->diag.ensure(sx * n));
@@ -339,7 +350,7 @@ void jacobi_options_default(jacobi_options* o) {
     o->inner_rel_tol = 1e-3;
     o->max_inner = 200;
     o->max_outer = 50;
-    o->refine_tol = 1e-10;
+    o->refine_tol = 1e-11;
     o->sync_every = 0;
     o->profile = 0;
 }
@@ -420,7 +431,7 @@ jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k, int32_t a_dtyp
         if (o.mode == JACOBI_MODE_REFINE)
             st = solve_refine(c, n, k, A, lda, B, ldb, X0, X, ldx, o, stream, info);
         else
-            st = solve_plain(c, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, stream, info);
+            st = solve_plain_locked(c, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, stream, info);
         info->status = st;
         return st;
     } catch (...) {

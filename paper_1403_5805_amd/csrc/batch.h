@@ -1,0 +1,43 @@
+// Host-side declarations of the batched (persistent MFMA) solver.
+#pragma once
+
+#include <vector>
+
+#include "ctx.h"
+
+namespace jac {
+
+// One system handed to the persistent kernel (device pointers, FP32 B/X).
+struct BatchItem {
+    int64_t n, k;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    const void* X0;
+    void* X;
+    int64_t ldx;
+    int32_t max_iter;
+};
+
+// Workgroup plan: jobs of workgroup g are jobs[job_off[g] .. job_off[g+1]).
+struct Plan {
+    std::vector<int> nwg;        // workgroups per system
+    std::vector<BJob> jobs;
+    std::vector<int32_t> job_off;
+    int grid = 0;
+    int max_nwg = 1;
+};
+
+Plan make_plan(const std::vector<int64_t>& n, int capacity);
+
+jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
+                          const jacobi_options& o, int32_t test, double rel, hipStream_t s,
+                          jacobi_info* infos);
+
+jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_dtype,
+                                 const void* A, int64_t lda, const void* B, int64_t ldb,
+                                 const void* X0, void* X, int64_t ldx, const jacobi_options& o,
+                                 hipStream_t s, jacobi_info* info);
+
+}  // namespace jac

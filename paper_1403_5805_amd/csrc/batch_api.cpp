@@ -1,0 +1,331 @@
+// Host side of the batched solver: argument checks, the workgroup plan for the
+// persistent MFMA kernel, workspaces, and per-system outcomes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+#include "batch.h"
+#include "ctx.h"
+
+namespace jac {
+
+#define HIP_TRY(expr)                                                               \
+    do {                                                                            \
+        hipError_t _e = (expr);                                                     \
+        if (_e != hipSuccess) {                                                     \
+            set_error("%s failed: %s", #expr, hipGetErrorString(_e));               \
+            return _e == hipErrorOutOfMemory ? JACOBI_ERR_OUT_OF_MEMORY             \
+                                             : JACOBI_ERR_DEVICE;                   \
+        }                                                                           \
+    } while (0)
+
+static double bits_to_double(uint64_t b) {
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// Split rows of big systems over several workgroups and pack small systems
+// whole into the remaining workgroups (longest-processing-time first).
+// Weights are the bytes of A streamed per sweep.  A workgroup that shares a
+// system with others owns nothing else, so barrier waits only involve
+// workgroups that are certain to arrive.
+Plan make_plan(const std::vector<int64_t>& n, int capacity) {
+    Plan p;
+    const int count = (int)n.size();
+    p.nwg.assign(count, 1);
+    if (count == 0) {
+        p.job_off.push_back(0);
+        return p;
+    }
+    double total = 0.0;
+    for (int64_t v : n) total += (double)v * (double)v;
+    const double target = total / std::max(1, capacity);
+    std::vector<int> big, small;
+    int g_big = 0;
+    for (int i = 0; i < count; ++i) {
+        const double w = (double)n[i] * (double)n[i];
+        const int64_t tiles = (n[i] + 15) / 16;
+        int want = (int)std::ceil(w / target);
+        want = (int)std::min<int64_t>(want, tiles);
+        if (want >= 2) {
+            p.nwg[i] = want;
+            big.push_back(i);
+            g_big += want;
+        } else {
+            small.push_back(i);
+        }
+    }
+    const int reserve = small.empty() ? 0 : std::max(1, std::min((int)small.size(), capacity / 8));
+    while (g_big > capacity - reserve && !big.empty()) {
+        // shrink the largest shares until the plan fits the resident grid
+        int best = big[0];
+        for (int i : big)
+            if (p.nwg[i] > p.nwg[best]) best = i;
+        p.nwg[best] -= 1;
+        g_big -= 1;
+        if (p.nwg[best] == 1) {
+            big.erase(std::find(big.begin(), big.end(), best));
+            small.push_back(best);
+            g_big -= 1;
+        }
+    }
+    std::vector<std::vector<BJob>> wg_jobs;
+    for (int i : big) {
+        const int64_t tiles = (n[i] + 15) / 16;
+        for (int r = 0; r < p.nwg[i]; ++r) {
+            const int64_t t0 = tiles * r / p.nwg[i], t1 = tiles * (r + 1) / p.nwg[i];
+            BJob j;
+            j.sys = i;
+            j.rank = r;
+            j.r0 = (int32_t)(16 * t0);
+            j.r1 = (int32_t)std::min<int64_t>(n[i], 16 * t1);
+            wg_jobs.push_back({j});
+        }
+    }
+    const int bins = std::max(small.empty() ? 0 : 1,
+                              std::min((int)small.size(), capacity - (int)wg_jobs.size()));
+    if (bins > 0) {
+        std::sort(small.begin(), small.end(), [&](int a, int b) { return n[a] > n[b]; });
+        using Item = std::pair<double, int>;
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+        const size_t base = wg_jobs.size();
+        wg_jobs.resize(base + bins);
+        for (int b = 0; b < bins; ++b) heap.push({0.0, b});
+        for (int i : small) {
+            Item it = heap.top();
+            heap.pop();
+            BJob j;
+            j.sys = i;
+            j.rank = 0;
+            j.r0 = 0;
+            j.r1 = (int32_t)n[i];
+            wg_jobs[base + it.second].push_back(j);
+            it.first += (double)n[i] * (double)n[i];
+            heap.push(it);
+        }
+    }
+    p.job_off.push_back(0);
+    for (auto& v : wg_jobs) {
+        if (v.empty()) continue;
+        for (auto& j : v) p.jobs.push_back(j);
+        p.job_off.push_back((int32_t)p.jobs.size());
+    }
+    p.grid = (int)p.job_off.size() - 1;
+    p.max_nwg = 1;
+    for (int v : p.nwg) p.max_nwg = std::max(p.max_nwg, v);
+    return p;
+}
+
+// Run the persistent MFMA kernel on `count` FP32/BF16 systems (k <= 32).
+// infos[i] receives each system's outcome.
+jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
+                          const jacobi_options& o, int32_t test, double rel, hipStream_t s,
+                          jacobi_info* infos) {
+    int kmax = 1;
+    int64_t nmax = 1;
+    for (int i = 0; i < count; ++i) {
+        kmax = std::max<int>(kmax, (int)items[i].k);
+        nmax = std::max(nmax, items[i].n);
+    }
+    const int kt = kmax <= 16 ? 16 : 32;
+    const int capacity = batched_max_grid(a_dtype, kt, c->num_cus);
+    if (capacity < 1) {
+        set_error("batched kernel unavailable for this dtype");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    std::vector<int64_t> ns(count);
+    for (int i = 0; i < count; ++i) ns[i] = items[i].n;
+    Plan plan = make_plan(ns, capacity);
+
+    // workspace: per system buf0, buf1 (n*kt) and diag (n), 256-byte aligned
+    std::vector<size_t> off(count);
+    size_t ws = 0;
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    for (int i = 0; i < count; ++i) {
+        off[i] = ws;
+        ws += 2 * align(sizeof(float) * items[i].n * kt) + align(sizeof(float) * items[i].n);
+    }
+    const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
+    const size_t job_b = align(sizeof(BJob) * std::max<size_t>(1, plan.jobs.size()));
+    const size_t off_b = align(sizeof(int32_t) * plan.job_off.size());
+    const size_t parts_b = align(sizeof(double) * 2 * (size_t)count * plan.max_nwg);
+    HIP_TRY(c->bws.ensure(ws));
+    HIP_TRY(c->bmeta.ensure(sys_b + st_b + job_b + off_b + parts_b));
+    char* meta = (char*)c->bmeta.p;
+    BSys* d_sys = (BSys*)meta;
+    BState* d_st = (BState*)(meta + sys_b);
+    BJob* d_jobs = (BJob*)(meta + sys_b + st_b);
+    int32_t* d_off = (int32_t*)(meta + sys_b + st_b + job_b);
+    double* d_parts = (double*)(meta + sys_b + st_b + job_b + off_b);
+
+    std::vector<BSys> hs(count);
+    std::vector<BState> hst(count);
+    for (int i = 0; i < count; ++i) {
+        const BatchItem& it = items[i];
+        char* base = (char*)c->bws.p + off[i];
+        BSys& S = hs[i];
+        std::memset(&S, 0, sizeof(S));
+        S.A = it.A;
+        S.lda = it.lda;
+        S.B = (const float*)it.B;
+        S.ldb = it.ldb;
+        S.X = (float*)it.X;
+        S.ldx = it.ldx;
+        S.X0 = (const float*)it.X0;
+        S.buf0 = (float*)base;
+        S.buf1 = (float*)(base + align(sizeof(float) * it.n * kt));
+        S.diag = (const float*)(base + 2 * align(sizeof(float) * it.n * kt));
+        S.n = it.n;
+        S.k = (int32_t)it.k;
+        S.nwg = plan.nwg[i];
+        S.max_iter = it.max_iter;
+        S.test = test;
+        S.tol = o.tol;
+        S.rel = rel;
+        S.norm = o.norm;
+        const size_t ea = a_dtype == JACOBI_F32 ? 4 : 2;
+        S.aligned = (((uintptr_t)it.A % 16) == 0 && ((size_t)it.lda * ea) % 16 == 0) ? 1 : 0;
+        BState& T = hst[i];
+        std::memset(&T, 0, sizeof(T));
+        T.bad_diag = INT64_MAX;
+        T.bad_rhs = INT64_MAX;
+    }
+    HIP_TRY(hipMemcpyAsync(d_sys, hs.data(), sizeof(BSys) * count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_st, hst.data(), sizeof(BState) * count, hipMemcpyHostToDevice, s));
+    if (!plan.jobs.empty())
+        HIP_TRY(hipMemcpyAsync(d_jobs, plan.jobs.data(), sizeof(BJob) * plan.jobs.size(),
+                               hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_off, plan.job_off.data(), sizeof(int32_t) * plan.job_off.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(c->ev_begin, s));
+    HIP_TRY(launch_batched_setup(a_dtype, kt, d_sys, d_st, count, nmax, s));
+    BatchArgs ba{};
+    ba.sys = d_sys;
+    ba.st = d_st;
+    ba.jobs = d_jobs;
+    ba.job_off = d_off;
+    ba.parts = d_parts;
+    ba.max_nwg = plan.max_nwg;
+    ba.count = count;
+    ba.chunk = batched_chunk(kt);
+    int rate_khz = 100000;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
+    if (plan.grid > 0) HIP_TRY(launch_batched(a_dtype, kt, ba, plan.grid, s));
+    HIP_TRY(hipEventRecord(c->ev_end, s));
+    HIP_TRY(hipMemcpyAsync(hst.data(), d_st, sizeof(BState) * count, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_begin, c->ev_end));
+    for (int i = 0; i < count; ++i) {
+        jacobi_info& inf = infos[i];
+        const BState& T = hst[i];
+        inf.device_ms = ms;
+        inf.rel_residual = -1.0;
+        inf.bad_index = -1;
+        if (T.bad_diag != INT64_MAX) {
+            inf.bad_index = T.bad_diag / 2;
+            inf.status = (T.bad_diag & 1) ? JACOBI_ERR_NONFINITE_INPUT : JACOBI_ERR_ZERO_DIAGONAL;
+            inf.iterations = 0;
+            inf.final_delta = -1.0;
+            continue;
+        }
+        if (T.bad_rhs != INT64_MAX) {
+            inf.bad_index = T.bad_rhs;
+            inf.status = JACOBI_ERR_NONFINITE_INPUT;
+            inf.iterations = 0;
+            inf.final_delta = -1.0;
+            continue;
+        }
+        if (T.error) {
+            inf.status = JACOBI_ERR_INTERNAL;
+            continue;
+        }
+        inf.iterations = T.iterations;
+        inf.final_delta = T.iterations > 0 ? bits_to_double(T.final_delta) : -1.0;
+        if (T.status == STOP_CONVERGED)
+            inf.status = JACOBI_OK;
+        else if (T.status == STOP_DIVERGED)
+            inf.status = JACOBI_DIVERGED;
+        else
+            inf.status = JACOBI_NOT_CONVERGED;
+    }
+    return JACOBI_OK;
+}
+
+}  // namespace jac
+
+using namespace jac;
+
+extern "C" jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count,
+                                              const jacobi_system* systems, int32_t a_dtype,
+                                              const jacobi_options* opt, hipStream_t stream,
+                                              jacobi_info* infos) {
+    try {
+        if (count < 0 || (count > 0 && (!systems || !infos))) {
+            set_error("invalid count or null array");
+            return JACOBI_ERR_INVALID_ARG;
+        }
+        jacobi_options o;
+        jacobi_options_default(&o);
+        if (opt) o = *opt;
+        for (int i = 0; i < count; ++i) {
+            std::memset(&infos[i], 0, sizeof(jacobi_info));
+            infos[i].status = JACOBI_ERR_INVALID_ARG;
+            infos[i].bad_index = -1;
+            infos[i].final_delta = -1.0;
+            infos[i].rel_residual = -1.0;
+        }
+        if (std::isnan(o.tol) || o.tol < 0.0 || o.max_iter < 0 ||
+            (o.norm != JACOBI_NORM_INF && o.norm != JACOBI_NORM_L2) ||
+            o.mode != JACOBI_MODE_PLAIN || (a_dtype != JACOBI_F64 && a_dtype != JACOBI_F32 &&
+                                            a_dtype != JACOBI_BF16)) {
+            set_error("invalid batched options (plain mode, tol >= 0, max_iter >= 0)");
+            return JACOBI_ERR_INVALID_ARG;
+        }
+        jacobi_status st = JACOBI_OK;
+        jacobi_ctx* c = ctx ? ctx : default_ctx(&st);
+        if (!c) return st;
+        std::lock_guard<std::mutex> g(c->mu);
+        if (hipSetDevice(c->device) != hipSuccess) return JACOBI_ERR_DEVICE;
+        std::vector<BatchItem> items;
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i) {
+            const jacobi_system& y = systems[i];
+            const bool ok = y.n >= 1 && y.k >= 1 && y.lda >= y.n && y.ldb >= y.k &&
+                            y.ldx >= y.k && y.A && y.B && y.X && y.n <= (int64_t)INT32_MAX &&
+                            (a_dtype == JACOBI_F64 || y.k <= 32);
+            if (!ok) continue;
+            BatchItem it{y.n, y.k, y.A, y.lda, y.B, y.ldb, y.X0, y.X, y.ldx, o.max_iter};
+            items.push_back(it);
+            idx.push_back(i);
+        }
+        if (items.empty()) return JACOBI_OK;
+        if (a_dtype == JACOBI_F64) {
+            // FP64 systems: the plain per-system path, one solve after another.
+            for (size_t q = 0; q < items.size(); ++q) {
+                const BatchItem& it = items[q];
+                solve_plain_locked(c, it.n, it.k, a_dtype, it.A, it.lda, it.B, it.ldb, it.X0, it.X,
+                                   it.ldx, o, stream, &infos[idx[q]]);
+            }
+            return JACOBI_OK;
+        }
+        std::vector<jacobi_info> out(items.size());
+        st = run_batched(c, (int32_t)items.size(), items.data(), a_dtype, o, TEST_ABS, 0.0,
+                         stream, out.data());
+        if (st != JACOBI_OK) return st;
+        for (size_t q = 0; q < items.size(); ++q) infos[idx[q]] = out[q];
+        return JACOBI_OK;
+    } catch (...) {
+        set_error("internal exception");
+        return JACOBI_ERR_INTERNAL;
+    }
+}

@@ -36,6 +36,8 @@ struct jacobi_ctx {
     jac::DevBuf diag, w0, w1;
     // refinement
     jac::DevBuf alo, diag_lo, xa, xb, r64, rlo, d0, d1, scal;
+    // batched solver: per-system buffers and descriptors
+    jac::DevBuf bws, bmeta;
 };
 
 namespace jac {

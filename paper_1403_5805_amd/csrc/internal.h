@@ -64,6 +64,7 @@ struct SweepArgs {
     int32_t seq;       // launch number within the current phase (selects the slot)
     int32_t aligned;   // 1: rows of A are 16-byte aligned (vector loads allowed)
     int64_t chunk;     // columns of x staged in LDS at once
+    int64_t rows_per_wg;  // rows owned by one workgroup (contiguous block)
     int32_t kpad;      // leading dimension of the iterate buffers (>= k)
     Ctl* ctl;
     Slot* slots;       // [2]
@@ -81,10 +82,12 @@ struct SweepArgs {
 
 // Host-side launch configuration chosen per call.
 struct LaunchCfg {
-    int waves;     // waves per workgroup
-    int rows;      // rows per wave
-    int64_t chunk; // columns of x staged in LDS at once
-    int grid;      // workgroups along rows
+    int waves;       // waves per workgroup (all waves share each row)
+    int rows;        // rows accumulated together by every wave
+    int unroll;      // 16-byte loads per row kept in flight by every lane
+    int64_t chunk;   // columns of x staged in LDS at once
+    int grid;        // workgroups along rows
+    int64_t rows_per_wg;  // contiguous rows owned by one workgroup
 };
 
 // Kernel launchers (defined in sweep.hip).  Return hipSuccess or the launch error.
@@ -105,6 +108,74 @@ hipError_t launch_copy_rows(int32_t elem_bytes, const void* src, int64_t lds, vo
                             int64_t ldd, int64_t n, int32_t k, hipStream_t s);
 hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t n, int32_t k,
                             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched persistent sweeps (MFMA tiles), one launch for many systems.
+
+// Per-system descriptor (device copy).  A is FP32 or BF16 (the launch's
+// dtype); B, X and the iterate buffers are FP32.  Iterate buffers have
+// leading dimension kt (16 or 32) with zero padding columns.
+struct BSys {
+    const void* A;
+    int64_t lda;
+    const float* B;
+    int64_t ldb;
+    float* X;          // caller's output (ldx), written once at the end
+    int64_t ldx;
+    const float* X0;   // caller's initial approximation (ldx), or null for zero
+    float* buf0;       // x^(0) on entry; ping-pong with buf1
+    float* buf1;
+    const float* diag;
+    int64_t n;
+    int32_t k;
+    int32_t nwg;       // workgroups sharing this system (1 = owned by one WG)
+    int32_t max_iter;
+    int32_t test;      // TEST_ABS or TEST_REL
+    double tol;        // TEST_ABS threshold
+    double rel;        // TEST_REL factor
+    int32_t norm;      // 0 inf, 1 l2
+    int32_t aligned;   // rows of A 16-byte aligned
+};
+
+// Per-system control state (device), zeroed before the launch.
+struct alignas(64) BState {
+    uint32_t counter;        // barrier arrivals (split systems)
+    uint32_t status;         // STOP_* (STOP_RUNNING = cap reached / not started)
+    int32_t iterations;      // sweeps executed
+    uint32_t error;          // 1: a barrier wait timed out
+    uint64_t dmax[3];        // per-sweep max |dx| (double bits), slot = sweep % 3
+    uint64_t xmax[3];        // per-sweep max |x_new|
+    uint64_t final_delta;    // double bits
+    int64_t bad_diag;        // validation: min over bad diagonals of 2*row + (non-finite ? 1 : 0)
+    int64_t bad_rhs;         // validation: first row with a non-finite B or X0 entry
+};
+
+// One unit of work for a workgroup: rows [r0, r1) of system sys.
+struct BJob {
+    int32_t sys;
+    int32_t rank;   // index of this workgroup among the system's workgroups
+    int32_t r0;
+    int32_t r1;
+};
+
+struct BatchArgs {
+    const BSys* sys;
+    BState* st;
+    const BJob* jobs;
+    const int32_t* job_off;   // [grid + 1]: jobs of workgroup g are [job_off[g], job_off[g+1])
+    double* parts;            // [2][count][max_nwg] L2 partial sums
+    int32_t max_nwg;
+    int32_t count;
+    int32_t chunk;            // x rows staged in LDS per chunk (multiple of 32)
+    int64_t spin_limit;       // wall-clock ticks (100 MHz) before a barrier wait gives up
+};
+
+hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,
+                                int32_t count, int64_t max_n, hipStream_t s);
+hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int grid,
+                          hipStream_t s);
+int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus);
+int batched_chunk(int32_t kt);
 
 // Default launch configuration for a sweep of this shape.
 LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus);

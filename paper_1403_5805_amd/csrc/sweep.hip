@@ -28,6 +28,8 @@
 //     x += d fused into the staging of x.
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "internal.h"
 
@@ -252,77 +254,36 @@ __device__ __forceinline__ void stage_x(TX* __restrict__ xs, const TX* __restric
 
 // ---------------------------------------------------------------------------
 // Accumulate sum_j alpha_ij x_j over columns [c0, c0 + cl) for the R rows
-// i0..i0+R-1 of this wave.  MODE 0 skips j == i (sec. 2: the sum runs over
-// j != i); MODE 1 (residual) keeps every term.
-template <typename TA, typename TX, int KT, int R, int MODE>
+// g..g+R-1 (the same rows for every wave of the workgroup).  The columns are
+// cut into span blocks of 64*VEC; wave w takes blocks w, w+W, w+2W, ... so the
+// W waves together read W consecutive 1 KiB pieces of each row per load.
+// MODE 0 skips j == i (sec. 2: the sum runs over j != i); MODE 1 (residual)
+// keeps every term.
+template <typename TA, typename TX, int KT, int R, int U, int W, int MODE>
 __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restrict__ A, int64_t lda,
-                                           int64_t n, int64_t i0, int64_t c0, int64_t cl,
-                                           const TX* __restrict__ xs, int lane, bool aligned) {
+                                           int64_t n, int64_t g, int64_t c0, int64_t cl,
+                                           const TX* __restrict__ xs, int lane, int wave,
+                                           bool aligned) {
     constexpr int VEC = Elem<TA>::vec;
     constexpr int SPAN = 64 * VEC;
-    constexpr int U = (R * KT * (int)sizeof(TX) <= 32) ? 2 : 1;
-    constexpr int NV = (VEC * KT * (int)sizeof(TX)) / 16;  // LDS 16-byte reads per column group
+    constexpr int NV = (VEC * KT * (int)sizeof(TX)) / 16;  // LDS 16-byte reads per load
     static_assert(NV >= 1, "x slice must be at least 16 bytes");
     const TA* rowp[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t i = (i0 + r < n) ? (i0 + r) : (n - 1);
-        rowp[r] = A + i * lda + c0;
+        const int64_t i = (g + r < n) ? (g + r) : (n - 1);
+        rowp[r] = A + i * lda + c0 + lane * VEC;
     }
-    const int64_t nfull = aligned ? (cl / SPAN) : 0;
-    const int64_t dlo = i0 - c0;  // diagonal of row i0+r sits at relative column dlo+r
-    int64_t it = 0;
-    for (; it + U <= nfull; it += U) {
-        u32x4 v[U][R];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                v[u][r] = __builtin_nontemporal_load(
-                    reinterpret_cast<const u32x4*>(rowp[r] + (it + u) * SPAN + lane * VEC));
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t cbase = (it + u) * SPAN;
-            const int64_t col = cbase + (int64_t)lane * VEC;
-            TX xv[VEC * KT];
-            {
-                u32x4 t[NV];
-                const u32x4* src = reinterpret_cast<const u32x4*>(xs + col * KT);
-#pragma unroll
-                for (int q = 0; q < NV; ++q) t[q] = src[q];
-                __builtin_memcpy(xv, t, sizeof(xv));
-            }
-            TX a[R][VEC];
-#pragma unroll
-            for (int r = 0; r < R; ++r) unpack16<TA, TX>(v[u][r], a[r]);
-            if (MODE == 0 && cbase < dlo + R && dlo < cbase + SPAN) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        if (col + e == dlo + r) a[r][e] = (TX)0;
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e)
-#pragma unroll
-                    for (int c = 0; c < KT; ++c)
-                        acc[r][c] = tx_fma(a[r][e], xv[e * KT + c], acc[r][c]);
-        }
-    }
-    for (; it < nfull; ++it) {
-        u32x4 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[r] = __builtin_nontemporal_load(
-                reinterpret_cast<const u32x4*>(rowp[r] + it * SPAN + lane * VEC));
-        const int64_t cbase = it * SPAN;
-        const int64_t col = cbase + (int64_t)lane * VEC;
+    const int64_t nsb = aligned ? (cl / SPAN) : 0;           // full span blocks
+    const int64_t nj = nsb > wave ? (nsb - wave + W - 1) / W : 0;  // blocks of this wave
+    const int64_t dlo = g - c0;  // diagonal of row g+r sits at relative column dlo+r
+
+    auto consume = [&](const u32x4 (&v)[R], int64_t sb) {
+        const int64_t cbase = sb * SPAN;
         TX xv[VEC * KT];
         {
             u32x4 t[NV];
-            const u32x4* src = reinterpret_cast<const u32x4*>(xs + col * KT);
+            const u32x4* src = reinterpret_cast<const u32x4*>(xs + (cbase + (int64_t)lane * VEC) * KT);
 #pragma unroll
             for (int q = 0; q < NV; ++q) t[q] = src[q];
             __builtin_memcpy(xv, t, sizeof(xv));
@@ -331,6 +292,7 @@ __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restric
 #pragma unroll
         for (int r = 0; r < R; ++r) unpack16<TA, TX>(v[r], a[r]);
         if (MODE == 0 && cbase < dlo + R && dlo < cbase + SPAN) {
+            const int64_t col = cbase + (int64_t)lane * VEC;
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -343,15 +305,37 @@ __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restric
             for (int e = 0; e < VEC; ++e)
 #pragma unroll
                 for (int c = 0; c < KT; ++c) acc[r][c] = tx_fma(a[r][e], xv[e * KT + c], acc[r][c]);
+    };
+
+    int64_t j = 0;
+    for (; j + U <= nj; j += U) {
+        u32x4 v[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t sb = wave + (j + u) * W;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[u][r] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rowp[r] + sb * SPAN));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) consume(v[u], wave + (j + u) * W);
     }
-    // Ragged tail (and the whole row when rows are not 16-byte aligned).
-    for (int64_t col = nfull * SPAN + lane; col < cl; col += 64) {
+    for (; j < nj; ++j) {
+        u32x4 v[R];
+        const int64_t sb = wave + j * W;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(rowp[r] + sb * SPAN));
+        consume(v, sb);
+    }
+    // Ragged tail (and whole rows when they are not 16-byte aligned).
+    for (int64_t col = nsb * SPAN + wave * 64 + lane; col < cl; col += W * 64) {
         TX xv[KT];
 #pragma unroll
         for (int c = 0; c < KT; ++c) xv[c] = xs[col * KT + c];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            TX a = widen<TA, TX>(rowp[r][col]);
+            TX a = widen<TA, TX>(rowp[r][col - lane * VEC]);
             if (MODE == 0 && col == dlo + r) a = (TX)0;
 #pragma unroll
             for (int c = 0; c < KT; ++c) acc[r][c] = tx_fma(a, xv[c], acc[r][c]);
@@ -456,11 +440,26 @@ __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax,
 }
 
 // ---------------------------------------------------------------------------
+// Rows per pass: the cross-wave partial sums of one pass live in LDS.
+template <typename TX, int KT, int W, int R>
+constexpr int pass_rows() {
+    int p = 8192 / (KT * W * (int)sizeof(TX));
+    if (p > 64) p = 64;
+    if (p < R) p = R;
+    return (p / R) * R;
+}
+
 // The sweep (MODE 0) / residual (MODE 1) kernel.
-//   grid.x : row blocks of W*R rows (grid-stride when fewer workgroups)
+//   grid.x : contiguous blocks of rows_per_wg rows (grid-stride if fewer WGs)
 //   grid.y : column groups of KT right-hand sides (k > 32 only)
-template <typename TA, typename TX, int KT, int R, int W, int MODE>
-__global__ __launch_bounds__(W * 64, (R * KT * sizeof(TX) <= 64) ? 4 : 2) void k_sweep(SweepArgs p) {
+// Every wave of a workgroup works on the same R rows at a time (on different
+// columns); each wave folds its lane sums into its own LDS slot per row, and
+// after each pass of P rows one thread per (row, column) adds the W slots in
+// wave order and applies the epilogue.
+template <typename TA, typename TX, int KT, int R, int U, int W, int MODE>
+__global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
+    constexpr int P = pass_rows<TX, KT, W, R>();
+    __shared__ TX red[P * KT * W];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     TX* xs = reinterpret_cast<TX*>(lds_raw);
     if (ld_stop(p.ctl) != STOP_RUNNING) return;
@@ -475,14 +474,8 @@ __global__ __launch_bounds__(W * 64, (R * KT * sizeof(TX) <= 64) ? 4 : 2) void k
     const TX* xin = reinterpret_cast<const TX*>(p.xin);
     const TX* diag = reinterpret_cast<const TX*>(p.diag);
     const bool aligned = p.aligned != 0;
-    // Column groups (k > KT) stage a strided slice; for one group the iterate
-    // rows are contiguous with leading dim KT.
     const TX* xsrc = xin + cb;
     const float* dsrc = (MODE == 1 && p.dlt) ? (p.dlt + cb) : nullptr;
-
-    uint64_t dmax = 0, xmax = 0;
-    double sq = 0.0;
-    const bool single = p.chunk >= n;
     const bool contiguous = (kp == KT);
 
     auto stage = [&](int64_t c0, int64_t cl) {
@@ -502,66 +495,77 @@ __global__ __launch_bounds__(W * 64, (R * KT * sizeof(TX) <= 64) ? 4 : 2) void k
         }
     };
 
+    uint64_t dmax = 0, xmax = 0;
+    double sq = 0.0;
+    const bool single = p.chunk >= n;
     if (single) {
         stage(0, n);
         __syncthreads();
     }
-    const int64_t rpb = (int64_t)W * R;
-    for (int64_t rb = (int64_t)blockIdx.x * rpb; rb < n; rb += (int64_t)gridDim.x * rpb) {
-        const int64_t i0 = rb + (int64_t)wave * R;
-        TX acc[R][KT];
+    const int64_t rpw = p.rows_per_wg;
+    for (int64_t rb = (int64_t)blockIdx.x * rpw; rb < n; rb += (int64_t)gridDim.x * rpw) {
+        const int64_t rbe = (rb + rpw) < n ? (rb + rpw) : n;
+        for (int64_t ps = rb; ps < rbe; ps += P) {
+            const int64_t pe = (ps + P) < rbe ? (ps + P) : rbe;
+            for (int t = lane; t < P * KT; t += 64) red[t * W + wave] = (TX)0;
+            for (int64_t c0 = 0; c0 < n; c0 += p.chunk) {
+                const int64_t cl = (n - c0) < p.chunk ? (n - c0) : p.chunk;
+                if (!single) {
+                    __syncthreads();
+                    stage(c0, cl);
+                    __syncthreads();
+                }
+                for (int64_t g = ps; g < pe; g += R) {
+                    TX acc[R][KT];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+                    for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int c = 0; c < KT; ++c) acc[r][c] = (TX)0;
-        for (int64_t c0 = 0; c0 < n; c0 += p.chunk) {
-            const int64_t cl = (n - c0) < p.chunk ? (n - c0) : p.chunk;
-            if (!single) {
-                __syncthreads();
-                stage(c0, cl);
-                __syncthreads();
-            }
-            if (i0 < n) accumulate<TA, TX, KT, R, MODE>(acc, A, p.lda, n, i0, c0, cl, xs, lane, aligned);
-        }
+                        for (int c = 0; c < KT; ++c) acc[r][c] = (TX)0;
+                    accumulate<TA, TX, KT, R, U, W, MODE>(acc, A, p.lda, n, g, c0, cl, xs, lane,
+                                                          wave, aligned);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+                    for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int c = 0; c < KT; ++c) acc[r][c] = wave_sum(acc[r][c]);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-#pragma unroll
-            for (int c = 0; c < KT; ++c) {
-                const int t = r * KT + c;
-                const int64_t i = i0 + r;
-                if ((t & 63) == lane && i < n && c < kc) {
-                    const TX s = acc[r][c];
-                    if (MODE == 0) {
-                        const TX b = B[i * p.ldb + cb + c];
-                        const TX xn = (b - s) / diag[i];
-                        const TX xo = xin[i * kp + cb + c];
-                        reinterpret_cast<TX*>(p.xout)[i * kp + cb + c] = xn;
-                        const double dd = fabs((double)xn - (double)xo);
-                        const double am = fabs((double)xn);
-                        const uint64_t db = dbits(dd), mb = dbits(am);
-                        dmax = db > dmax ? db : dmax;
-                        xmax = mb > xmax ? mb : xmax;
-                        sq += dd * dd;
-                    } else {
-                        // residual r = b - A x with x already updated in LDS;
-                        // the owner of row i also stores the updated x.
-                        const double b = (double)B[i * p.ldb + cb + c];
-                        const double rr = b - (double)s;
-                        p.r64[i * kp + cb + c] = rr;
-                        p.rlo[i * kp + cb + c] = (float)rr;
-                        double xnew = (double)xin[i * kp + cb + c];
-                        if (dsrc) xnew += (double)dsrc[i * kp + c];
-                        reinterpret_cast<double*>(p.xout)[i * kp + cb + c] = xnew;
-                        sq += rr * rr;
-                        const uint64_t mb = dbits(fabs(rr));
-                        dmax = mb > dmax ? mb : dmax;
-                    }
+                        for (int c = 0; c < KT; ++c) {
+                            const TX v = wave_sum(acc[r][c]);
+                            if (lane == 0 && g + r < pe)
+                                red[((g - ps + r) * KT + c) * W + wave] += v;
+                        }
                 }
             }
+            __syncthreads();
+            for (int t = tid; t < (int)(pe - ps) * KT; t += W * 64) {
+                const int64_t i = ps + t / KT;
+                const int c = t % KT;
+                if (c >= kc) continue;
+                TX s = (TX)0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) s += red[t * W + w];
+                if (MODE == 0) {
+                    const TX b = B[i * p.ldb + cb + c];
+                    const TX xn = (b - s) / diag[i];
+                    const TX xo = xin[i * kp + cb + c];
+                    reinterpret_cast<TX*>(p.xout)[i * kp + cb + c] = xn;
+                    const double dd = fabs((double)xn - (double)xo);
+                    const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                    dmax = db > dmax ? db : dmax;
+                    xmax = mb > xmax ? mb : xmax;
+                    sq += dd * dd;
+                } else {
+                    // residual r = b - A x with x already updated in LDS; the
+                    // owner of row i also stores the updated x.
+                    const double rr = (double)B[i * p.ldb + cb + c] - (double)s;
+                    p.r64[i * kp + cb + c] = rr;
+                    p.rlo[i * kp + cb + c] = (float)rr;
+                    double xnew = (double)xin[i * kp + cb + c];
+                    if (dsrc) xnew += (double)dsrc[i * kp + c];
+                    reinterpret_cast<double*>(p.xout)[i * kp + cb + c] = xnew;
+                    sq += rr * rr;
+                    const uint64_t mb = dbits(fabs(rr));
+                    dmax = mb > dmax ? mb : dmax;
+                }
+            }
+            __syncthreads();
         }
     }
     finish_launch<W>(p, dmax, xmax, sq);
@@ -685,29 +689,43 @@ hipError_t launch_setup(int32_t a_dtype, const void* A, int64_t lda, const void*
     return hipGetLastError();
 }
 
-template <typename TA, typename TX, int KT, int R, int W, int MODE>
+template <typename TA, typename TX, int KT, int R, int U, int W, int MODE>
 static hipError_t launch_one(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
-    if constexpr (R * KT * sizeof(TX) > 256) {
+    if constexpr (R * KT * sizeof(TX) > 256 || (R > 1 && R * KT * sizeof(TX) > 128) || R * U > 8) {
         return hipErrorInvalidValue;
     } else {
         const int gy = (a.k + KT - 1) / KT;
         const size_t lds = (size_t)a.chunk * KT * sizeof(TX);
-        hipLaunchKernelGGL((k_sweep<TA, TX, KT, R, W, MODE>), dim3(cfg.grid, gy), dim3(W * 64),
-                           lds, s, a);
+        auto kern = k_sweep<TA, TX, KT, R, U, W, MODE>;
+        static size_t lds_allowed = 0;  // dynamic LDS already enabled for this kernel
+        if (lds > 32768 && lds > lds_allowed) {
+            hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            lds_allowed = lds;
+        }
+        hipLaunchKernelGGL(kern, dim3(cfg.grid, gy), dim3(W * 64), lds, s, a);
         return hipGetLastError();
     }
 }
 
+template <typename TA, typename TX, int KT, int W, int MODE>
+static hipError_t launch_ru(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
+    const int r = cfg.rows, u = cfg.unroll;
+    if (r == 1 && u == 2) return launch_one<TA, TX, KT, 1, 2, W, MODE>(a, cfg, s);
+    if (r == 1 && u == 4) return launch_one<TA, TX, KT, 1, 4, W, MODE>(a, cfg, s);
+    if (r == 2 && u == 2) return launch_one<TA, TX, KT, 2, 2, W, MODE>(a, cfg, s);
+    if (r == 2 && u == 4) return launch_one<TA, TX, KT, 2, 4, W, MODE>(a, cfg, s);
+    if (r == 4 && u == 2) return launch_one<TA, TX, KT, 4, 2, W, MODE>(a, cfg, s);
+    return hipErrorInvalidValue;
+}
+
 template <typename TA, typename TX, int KT, int MODE>
 static hipError_t launch_rw(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
-    if (cfg.waves == 8) {
-        if (cfg.rows == 4) return launch_one<TA, TX, KT, 4, 8, MODE>(a, cfg, s);
-        if (cfg.rows == 2) return launch_one<TA, TX, KT, 2, 8, MODE>(a, cfg, s);
-        if (cfg.rows == 1) return launch_one<TA, TX, KT, 1, 8, MODE>(a, cfg, s);
-    } else if (cfg.waves == 4) {
-        if (cfg.rows == 4) return launch_one<TA, TX, KT, 4, 4, MODE>(a, cfg, s);
-        if (cfg.rows == 2) return launch_one<TA, TX, KT, 2, 4, MODE>(a, cfg, s);
-        if (cfg.rows == 1) return launch_one<TA, TX, KT, 1, 4, MODE>(a, cfg, s);
+    if (cfg.waves == 8) return launch_ru<TA, TX, KT, 8, MODE>(a, cfg, s);
+    if (cfg.waves == 4) return launch_ru<TA, TX, KT, 4, MODE>(a, cfg, s);
+    if constexpr (KT <= 2) {
+        if (cfg.waves == 16) return launch_ru<TA, TX, KT, 16, MODE>(a, cfg, s);
     }
     return hipErrorInvalidValue;
 }
@@ -735,6 +753,7 @@ hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cf
                         hipStream_t s) {
     SweepArgs p = a;
     p.chunk = cfg.chunk;
+    p.rows_per_wg = cfg.rows_per_wg;
     switch (a_dtype) {
         case 0: return launch_kt<double, double, 0>(p, cfg, s);
         case 1: return launch_kt<float, float, 0>(p, cfg, s);
@@ -746,6 +765,7 @@ hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cf
 hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
     SweepArgs p = a;
     p.chunk = cfg.chunk;
+    p.rows_per_wg = cfg.rows_per_wg;
     return launch_kt<double, double, 1>(p, cfg, s);
 }
 
@@ -807,32 +827,72 @@ hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t 
 // ---------------------------------------------------------------------------
 // Launch-shape heuristics.
 
+// Dynamic LDS for the x chunk: 64 KiB when a workgroup may use more than
+// 72 KiB of LDS (gfx950), else what is left after the static pass buffer.
+static int64_t lds_chunk_bytes() {
+    static int64_t cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        cached = v >= 73728 ? 65536 : (v - 8192 > 16384 ? v - 8192 : 16384);
+    }
+    return cached;
+}
+
 static int64_t span_of(int32_t a_dtype) { return a_dtype == 0 ? 128 : (a_dtype == 1 ? 256 : 512); }
 
 LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus) {
     LaunchCfg c;
     const int kt = kt_for(k);
     const int sx = (a_dtype == 0) ? 8 : 4;
-    c.waves = 8;
-    int r = 256 / (kt * sx);
-    c.rows = r >= 4 ? 4 : (r >= 2 ? 2 : 1);
-    // Prefer more workgroups over more rows per wave when the system is small.
-    while (c.rows > 1 && (n + (int64_t)c.waves * c.rows - 1) / ((int64_t)c.waves * c.rows) <
-                             2 * (int64_t)num_cus)
-        c.rows >>= 1;
-    if ((n + (int64_t)c.waves * c.rows - 1) / ((int64_t)c.waves * c.rows) < 2 * (int64_t)num_cus)
-        c.waves = 4;
     const int64_t span = span_of(a_dtype);
-    int64_t cap = 65536 / ((int64_t)kt * sx);
+    // Waves share each row: a short row cannot keep 8 waves busy.
+    c.waves = (n >= 8 * span) ? 8 : 4;
+    // Rows accumulated together and loads in flight per row.
+    if (kt * sx <= 8) {
+        c.rows = 2;
+        c.unroll = 2;
+    } else if (kt * sx <= 32) {
+        c.rows = 2;
+        c.unroll = 2;
+    } else {
+        c.rows = 1;
+        c.unroll = 2;
+    }
+    // x chunk staged in LDS (whole x when it fits in 64 KiB; the pass
+    // reduction adds at most 8 KiB of static LDS, so two workgroups fit a CU).
+    int64_t cap = lds_chunk_bytes() / ((int64_t)kt * sx);
     cap = (cap / span) * span;
     if (cap < span) cap = span;
     c.chunk = n <= cap ? n : cap;
-    const int64_t rpb = (int64_t)c.waves * c.rows;
-    int64_t nb = (n + rpb - 1) / rpb;
-    int64_t gcap = (int64_t)num_cus * 8;
+    // One workgroup per CU, each owning a contiguous block of rows (measured
+    // best for streaming: fewer concurrent row streams per HBM channel); small
+    // systems get at least one row group per workgroup.
+    int64_t gcap = (int64_t)num_cus;
     const int64_t gy = (k + 31) / 32;
     if (gcap * gy > kMaxParts) gcap = kMaxParts / gy;
-    c.grid = (int)(nb < gcap ? nb : gcap);
+    int64_t g = (n + c.rows - 1) / c.rows;
+    if (g > gcap) g = gcap;
+    if (g < 1) g = 1;
+    // Tuning override "waves,rows,unroll,wg_per_cu" (JACOBI_SWEEP_CFG).
+    if (const char* env = getenv("JACOBI_SWEEP_CFG")) {
+        int w = 0, r = 0, u = 0, wpc = 0;
+        if (sscanf(env, "%d,%d,%d,%d", &w, &r, &u, &wpc) == 4 &&
+            (w == 4 || w == 8 || (w == 16 && kt <= 2)) &&
+            (r == 1 || r == 2 || r == 4) && (u == 2 || u == 4) && wpc >= 1) {
+            c.waves = w;
+            c.rows = r;
+            c.unroll = u;
+            gcap = (int64_t)num_cus * wpc;
+            if (gcap * gy > kMaxParts) gcap = kMaxParts / gy;
+            g = (n + c.rows - 1) / c.rows;
+            if (g > gcap) g = gcap;
+        }
+    }
+    c.rows_per_wg = (n + g - 1) / g;
+    c.grid = (int)((n + c.rows_per_wg - 1) / c.rows_per_wg);
     return c;
 }
 

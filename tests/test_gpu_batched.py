@@ -1,0 +1,160 @@
+"""GPU parity of the persistent batched MFMA path (jacobi_solve_batched) and of
+multi-right-hand-side solves, against the FP64 oracle on the promoted
+systems; batch invariance and per-system failure isolation."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import REL_F32, dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def jac(gpu):
+    import paper_1403_5805_amd as jac
+    return jac
+
+
+def _sys32(n, k, seed, mode=synth.ADDITIVE, lo=1.0, hi=2.0):
+    A32, Xt, B32 = synth.dominant_f32(n, k, seed, mode, lo, hi)
+    return A32, Xt, B32
+
+
+def _oracle32(A32, B32, tol, cap=500):
+    return oracle.jacobi(A32.astype(np.float64), B32.astype(np.float64), tol=tol, max_iter=cap)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_mixed_batch_parity(jac, dtype):
+    """Uneven sizes (tiles, ragged tails, n < 16) and k in {1..32}."""
+    import torch
+    shapes = [(1, 1), (5, 3), (16, 16), (17, 32), (100, 1), (255, 7), (256, 32), (513, 16),
+              (1000, 4), (1201, 32)]
+    sysl, refs = [], []
+    for idx, (n, k) in enumerate(shapes):
+        A32, Xt, B32 = _sys32(n, k, 500 + idx)
+        if dtype == "bf16":
+            At = torch.from_numpy(A32).to(torch.bfloat16)
+            Ap = At.to(torch.float64).numpy()
+        else:
+            At = torch.from_numpy(A32)
+            Ap = A32.astype(np.float64)
+        xo, io = oracle.jacobi(Ap, B32.astype(np.float64), tol=1e-6, max_iter=500)
+        sysl.append((At.cuda(), dev(B32)))
+        refs.append((xo, io))
+    say("mixed batch", dtype)
+    xs, infos = jac.solve_batched(sysl, tol=1e-6, max_iter=500)
+    for (n, k), X, info, (xo, io) in zip(shapes, xs, infos, refs):
+        assert info["status"] == jac.OK, (n, k, info)
+        assert abs(info["iterations"] - io["iterations"]) <= 1, (n, k, info, io)
+        assert rel_err(host(X), xo) <= REL_F32, (n, k)
+
+
+def test_batch_invariance_bitwise(jac):
+    """A system gives bitwise the same X and count alone and inside a batch
+    (its own tiles, chunk order and max reduction do not depend on the batch)."""
+    import torch
+    shapes = [(700, 32), (64, 5), (2048, 16), (300, 1), (1500, 32)]
+    sysl = []
+    for idx, (n, k) in enumerate(shapes):
+        A32, _, B32 = _sys32(n, k, 900 + idx)
+        sysl.append((dev(A32), dev(B32)))
+    say("batch invariance")
+    xs, infos = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    for i, s in enumerate(sysl):
+        x1, i1 = jac.solve_batched([s], tol=1e-6, max_iter=200)
+        assert torch.equal(x1[0], xs[i]), shapes[i]
+        assert i1[0]["iterations"] == infos[i]["iterations"]
+    # the single-system entry point routes k >= 8 FP32 to the same kernel
+    X, info = jac.solve(sysl[0][0], sysl[0][1], tol=1e-6, max_iter=200)
+    assert torch.equal(X, xs[0]) and info["iterations"] == infos[0]["iterations"]
+
+
+def test_failures_isolated(jac):
+    """A zero diagonal / NaN right-hand side fails only its own system; its X
+    is untouched and its neighbours are bitwise unaffected."""
+    import torch
+    good = []
+    for idx, (n, k) in enumerate([(300, 4), (800, 16)]):
+        A32, _, B32 = _sys32(n, k, 1200 + idx)
+        good.append((dev(A32), dev(B32)))
+    A32, _, B32 = _sys32(200, 2, 1300)
+    Az = A32.copy(); Az[33, 33] = 0.0
+    Bn = B32.copy(); Bn[150, 1] = np.nan
+    bad1 = (dev(Az), dev(B32))
+    bad2 = (dev(A32), dev(Bn))
+    outs = [torch.empty_like(s[1]) for s in good] + [torch.full((200, 2), 3.0).cuda(),
+                                                      torch.full((200, 2), 3.0).cuda()]
+    say("failures isolated")
+    xs, infos = jac.solve_batched(good + [bad1, bad2], outs=outs, tol=1e-6, max_iter=200)
+    assert infos[2]["status"] == jac.ERR_ZERO_DIAGONAL and infos[2]["bad_index"] == 33
+    assert infos[3]["status"] == jac.ERR_NONFINITE_INPUT and infos[3]["bad_index"] == 150
+    assert torch.all(xs[2] == 3.0) and torch.all(xs[3] == 3.0)
+    ref, rinfo = jac.solve_batched(good, tol=1e-6, max_iter=200)
+    for a, b in zip(ref, xs[:2]):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,k", [(1000, 16), (777, 32), (4096, 8), (130, 31)])
+def test_multi_rhs_single_solve_mfma(jac, n, k):
+    """jacobi_solve with several right-hand sides in FP32 (MFMA tiles)."""
+    A32, _, B32 = _sys32(n, k, 1400 + n, synth.MULTIPLICATIVE, 0.5, 1.0)
+    xo, io = _oracle32(A32, B32, 1e-6)
+    say("multi rhs", n, k)
+    X, info = jac.solve(dev(A32), dev(B32), tol=1e-6, max_iter=500)
+    assert info["status"] == jac.OK
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert rel_err(host(X), xo) <= REL_F32
+    X2, info2 = jac.solve(dev(A32), dev(B32), tol=0.0, max_iter=3, norm="l2")
+    xo2, _ = _oracle32(A32, B32, 0.0, 3)
+    assert info2["iterations"] == 3 and rel_err(host(X2), xo2) <= REL_F32
+
+
+def test_c3_scaled(jac):
+    """Batched-uneven workload at reduced size: 32 systems, n log-uniform in
+    [256, 1024], k = 32, additive margin U[1,2], tol 1e-6."""
+    ns = synth.log_uniform_sizes(32, 256, 1024, synth.seed_for(2) + 77)
+    sysl, refs = [], []
+    for i, n in enumerate(ns):
+        A32, _, B32 = synth.c3_system(i, int(n))
+        sysl.append((dev(A32), dev(B32)))
+        refs.append((A32, B32))
+    say("c3 scaled")
+    xs, infos = jac.solve_batched(sysl, tol=1e-6, max_iter=1000)
+    for i in range(0, 32, 4):
+        A32, B32 = refs[i]
+        xo, io = _oracle32(A32, B32, 1e-6, 1000)
+        assert infos[i]["status"] == jac.OK
+        assert abs(infos[i]["iterations"] - io["iterations"]) <= 1
+        assert rel_err(host(xs[i]), xo) <= REL_F32
+
+
+def test_c3_full_size_properties(jac):
+    """The full batched workload (256 systems, n log-uniform in [256, 4096],
+    k = 32): every system converges and satisfies the fixed-point property
+    ||x - D^-1 (b - (A - D) x)||_inf <= 2 * Delta_final + O(u) (checked in FP64
+    with torch on the device); two systems are compared with the oracle."""
+    import torch
+    ns = synth.c3_sizes()
+    sysl = []
+    for i, n in enumerate(ns):
+        A32, _, B32 = synth.c3_system(i, int(n))
+        sysl.append((dev(A32), dev(B32)))
+    say("c3 full")
+    xs, infos = jac.solve_batched(sysl, tol=1e-6, max_iter=1000)
+    for (A, B), X, info in zip(sysl, xs, infos):
+        assert info["status"] == jac.OK, info
+        A64, B64, X64 = A.double(), B.double(), X.double()
+        d = torch.diagonal(A64)
+        fp = (B64 - (A64 @ X64 - d[:, None] * X64)) / d[:, None]
+        gap = (X64 - fp).abs().max().item()
+        assert gap <= 2 * info["final_delta"] + 1e-5 * X64.abs().max().item()
+    for i in (int(np.argmin(ns)), int(np.argmax(ns))):
+        A32, _, B32 = synth.c3_system(i, int(ns[i]))
+        xo, io = _oracle32(A32, B32, 1e-6, 1000)
+        assert abs(infos[i]["iterations"] - io["iterations"]) <= 1
+        assert rel_err(host(xs[i]), xo) <= REL_F32
