@@ -10,7 +10,14 @@ reductions and stop decisions, and the copy-out of X.  Inputs are resident in
 HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--sweeps 200]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--config c2|c1|c3|c4]
+
+The other configurations (--config) are measured with the same JSON layout:
+  c1  n = 512 FP64, tol 1e-10: solve latency (launch/sync bound)
+  c3  256 FP32 systems, n log-uniform in [256, 4096], k = 32: one persistent
+      batched MFMA launch per step (GB/s of A streamed and MFMA TF/s)
+  c4  n = 32768 FP64 system, BF16 sweeps inside FP64 iterative refinement:
+      time to ||r||/||b|| below target, bytes of all passes
 
 Prints one JSON line.  value = algorithmic bytes moved by all sweeps of all
 timed steps / wall time of the timed region (GB/s); the roofline object uses
@@ -68,6 +75,7 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-events", action="store_true")
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -81,6 +89,11 @@ def main() -> int:
 
     import paper_1403_5805_amd as jac
     import synth
+
+    if args.config != "c2":
+        res = {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4}[args.config](args)
+        print(json.dumps(res), flush=True)
+        return 0
 
     n = args.n
     dev = torch.device("cuda:0")
@@ -172,6 +185,169 @@ def main() -> int:
     print(json.dumps(res), flush=True)
     ctx.close()
     return 0
+
+
+def _common(args, metric, value, unit, ms_per_step, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, outs
+
+
+def bench_c1(args):
+    """n = 512 FP64, additive margin, tol 1e-10, cap 1000: solves per second."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1403_5805_amd as jac
+    import synth
+    A, Xt, B = synth.c1()
+    Ad, bd = torch.from_numpy(A).cuda(), torch.from_numpy(B[:, 0].copy()).cuda()
+    out = torch.empty_like(bd)
+    ctx = jac.Context(0)
+    steps = max(args.steps, 50)
+
+    def step():
+        _, info = jac.solve(Ad, bd, out=out, ctx=ctx, tol=1e-10, max_iter=1000)
+        return info
+    el, infos = _timed(step, steps, args.warmup)
+    info = infos[-1]
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 3.0:
+        xo, io = oracle.jacobi(A, B[:, 0], tol=1e-10, max_iter=1000)
+        reps += 1
+    cpu_dt = (time.perf_counter() - t0) / reps
+    err = float(np.abs(out.cpu().numpy() - xo).max() / np.abs(xo).max())
+    res = _common(args, "Jacobi solves/s (n=512 FP64, tol 1e-10)", round(steps / el, 1),
+                  "solves/s", round(el * 1e3 / steps, 4), "f64",
+                  {"workload": "dense FP64 Jacobi solve n=512, tol 1e-10 max-norm, cap 1000",
+                   "n": 512, "iterations": info["iterations"]})
+    res["steps"] = steps
+    res["us_per_sweep"] = round(el * 1e6 / steps / max(1, info["iterations"]), 2)
+    res["parity"] = {"oracle_iterations": io["iterations"], "iterations": info["iterations"],
+                     "rel_err_vs_oracle": err}
+    res["roofline"] = None
+    res["cpu_baseline"] = {"value": round(1.0 / cpu_dt, 1), "unit": "solves/s", "cores": 1,
+                           "kind": "oracle", "sample": f"{reps} oracle solves of the same system"}
+    ctx.close()
+    return res
+
+
+def bench_c3(args):
+    """256 FP32 systems, n log-uniform [256, 4096], k = 32, tol 1e-6: one
+    persistent batched launch per step."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1403_5805_amd as jac
+    import synth
+    ns = [int(v) for v in synth.c3_sizes()]
+    systems, host_sys = [], []
+    for i, n in enumerate(ns):
+        A32, _, B32 = synth.c3_system(i, n)
+        systems.append((torch.from_numpy(A32).cuda(), torch.from_numpy(B32).cuda()))
+        if i < 3:
+            host_sys.append((A32, B32))
+    outs = [torch.empty_like(s[1]) for s in systems]
+    ctx = jac.Context(0)
+
+    def step():
+        _, infos = jac.solve_batched(systems, outs=outs, ctx=ctx, tol=1e-6, max_iter=1000)
+        return infos
+    el, allinfo = _timed(step, args.steps, args.warmup)
+    infos = allinfo[-1]
+    ok = all(i["status"] == jac.OK for i in infos)
+    bytes_total = sum(i["iterations"] * (4 * n * n + 3 * 4 * n * 32) for n, i in zip(ns, infos))
+    flops_total = sum(i["iterations"] * 2 * n * n * 32 for n, i in zip(ns, infos))
+    dev_ms = infos[0]["device_ms"]
+    gbs = bytes_total / (dev_ms / 1e3) / 1e9
+    tfs = flops_total / (dev_ms / 1e3) / 1e12
+    # CPU baseline: the oracle on the first systems (FP64 on the promoted system)
+    t0 = time.perf_counter()
+    cpu_bytes = 0
+    for A32, B32 in host_sys:
+        _, io = oracle.jacobi(A32.astype(np.float64), B32.astype(np.float64), tol=1e-6,
+                              max_iter=1000)
+        n = A32.shape[0]
+        cpu_bytes += io["iterations"] * (4 * n * n + 3 * 4 * n * 32)
+    cpu_dt = time.perf_counter() - t0
+    res = _common(args, "batched Jacobi solves/s (256 FP32 systems, k=32)",
+                  round(len(ns) * args.steps / el, 1), "solves/s", round(el * 1e3 / args.steps, 3),
+                  "f32", {"workload": "256 dense FP32 systems, n log-uniform [256,4096], k=32, "
+                          "tol 1e-6, one persistent MFMA launch", "sum_n2": int(sum(n * n for n in ns)),
+                          "systems": len(ns)})
+    res["all_ok"] = ok
+    res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
+    res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                       "kernel": "k_batched<float,32,8,2>", "mfma_tflops": round(tfs, 2),
+                       "mfma_frac_of_157_3": round(tfs / 157.3, 4),
+                       "launch_device_ms": round(dev_ms, 3)}
+    res["cpu_baseline"] = {"value": round(cpu_bytes / cpu_dt / 1e9, 3), "unit": "GB/s",
+                           "cores": 1, "kind": "oracle",
+                           "sample": f"oracle solves of the first {len(host_sys)} systems, "
+                                     f"{cpu_dt:.2f} s"}
+    ctx.close()
+    return res
+
+
+def bench_c4(args):
+    """n = 32768 FP64, BF16 sweeps in FP64 iterative refinement."""
+    import numpy as np
+    import torch
+
+    import paper_1403_5805_amd as jac
+    import synth
+    n = 32768
+    A, Xt, B = synth.c4(n)
+    Ad = torch.from_numpy(A).cuda()
+    bd = torch.from_numpy(B[:, 0].copy()).cuda()
+    out = torch.empty_like(bd)
+    ctx = jac.Context(0)
+    steps = max(1, min(args.steps, 3))
+
+    def step():
+        _, info = jac.solve(Ad, bd, out=out, ctx=ctx, mode="refine", sweep_dtype="bf16")
+        return info
+    el, infos = _timed(step, steps, 1)
+    info = infos[-1]
+    err_true = float(np.abs(out.cpu().numpy() - Xt[:, 0]).max() / np.abs(Xt).max())
+    inner_b = 2 * n * n + 12 * n
+    resid_b = 8 * n * n + 24 * n
+    tot_b = info["iterations"] * inner_b + info["outer_iterations"] * resid_b
+    dev_ms = info["device_ms"]
+    res = _common(args, "mixed-precision refinement time to 1e-11 residual (n=32768)",
+                  round(dev_ms, 2), "ms", round(el * 1e3 / steps, 2), "bf16+f64",
+                  {"workload": "dense FP64 system n=32768 (A 8 GiB on device), BF16 copy "
+                               "(2 GiB) swept with FP32 accumulation inside FP64 refinement",
+                   "n": n}, higher=False)
+    res["steps"] = steps
+    res["outer_iterations"] = info["outer_iterations"]
+    res["inner_sweeps"] = info["iterations"]
+    res["rel_residual"] = info["rel_residual"]
+    res["rel_err_vs_x_true"] = err_true
+    res["effective_GBps"] = round(tot_b / (dev_ms / 1e3) / 1e9, 1)
+    res["roofline"] = {"bound": "hbm", "achieved": round(tot_b / (dev_ms / 1e3) / 1e9, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(tot_b / (dev_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "traffic": None, "kernel": "whole refinement call (residual + sweeps)"}
+    res["cpu_baseline"] = None
+    ctx.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -66,7 +66,7 @@ def _ld(t) -> int:
 
 
 def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype="bf16",
-                 inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-11,
+                 inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-12,
                  sync_every=0, profile=False) -> Options:
     o = Options()
     _lib.load().jacobi_options_default(ctypes.byref(o))

@@ -350,7 +350,7 @@ void jacobi_options_default(jacobi_options* o) {
     o->inner_rel_tol = 1e-3;
     o->max_inner = 200;
     o->max_outer = 50;
-    o->refine_tol = 1e-11;
+    o->refine_tol = 1e-12;
     o->sync_every = 0;
     o->profile = 0;
 }

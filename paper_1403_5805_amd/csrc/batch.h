@@ -29,7 +29,7 @@ struct Plan {
     int max_nwg = 1;
 };
 
-Plan make_plan(const std::vector<int64_t>& n, int capacity);
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw);
 
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
                           const jacobi_options& o, int32_t test, double rel, hipStream_t s,

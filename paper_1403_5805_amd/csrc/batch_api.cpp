@@ -30,12 +30,22 @@ static double bits_to_double(uint64_t b) {
     return d;
 }
 
-// Split rows of big systems over several workgroups and pack small systems
-// whole into the remaining workgroups (longest-processing-time first).
-// Weights are the bytes of A streamed per sweep.  A workgroup that shares a
-// system with others owns nothing else, so barrier waits only involve
-// workgroups that are certain to arrive.
-Plan make_plan(const std::vector<int64_t>& n, int capacity) {
+// Modelled time of one sweep of rows [0, rows) of an n-column system on one
+// workgroup: each wave walks ceil(tiles / W) 16-row tiles, each tile takes
+// ceil(blocks / U) load round trips plus its epilogue.  Units are arbitrary;
+// only ratios matter.
+static double job_cost(int64_t n, int64_t rows, int waves, int unroll, int bw) {
+    const double tiles_per_wave = std::ceil(std::ceil((double)rows / 16.0) / waves);
+    const double blocks = std::ceil((double)n / bw);
+    return tiles_per_wave * (1.0 + std::ceil(blocks / unroll)) + 1.0;
+}
+
+// Split big systems over several workgroups and pack small systems whole
+// into the remaining workgroups (longest-processing-time first), both by the
+// modelled sweep time above.  A workgroup that shares a system with others
+// owns nothing else, so barrier waits only involve workgroups that are certain
+// to arrive.
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw) {
     Plan p;
     const int count = (int)n.size();
     p.nwg.assign(count, 1);
@@ -43,15 +53,18 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity) {
         p.job_off.push_back(0);
         return p;
     }
+    std::vector<double> cost(count);
     double total = 0.0;
-    for (int64_t v : n) total += (double)v * (double)v;
+    for (int i = 0; i < count; ++i) {
+        cost[i] = job_cost(n[i], n[i], waves, unroll, bw);
+        total += cost[i];
+    }
     const double target = total / std::max(1, capacity);
     std::vector<int> big, small;
     int g_big = 0;
     for (int i = 0; i < count; ++i) {
-        const double w = (double)n[i] * (double)n[i];
         const int64_t tiles = (n[i] + 15) / 16;
-        int want = (int)std::ceil(w / target);
+        int want = (int)std::lround(cost[i] / target);
         want = (int)std::min<int64_t>(want, tiles);
         if (want >= 2) {
             p.nwg[i] = want;
@@ -91,7 +104,7 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity) {
     const int bins = std::max(small.empty() ? 0 : 1,
                               std::min((int)small.size(), capacity - (int)wg_jobs.size()));
     if (bins > 0) {
-        std::sort(small.begin(), small.end(), [&](int a, int b) { return n[a] > n[b]; });
+        std::sort(small.begin(), small.end(), [&](int a, int b) { return cost[a] > cost[b]; });
         using Item = std::pair<double, int>;
         std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
         const size_t base = wg_jobs.size();
@@ -106,7 +119,7 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity) {
             j.r0 = 0;
             j.r1 = (int32_t)n[i];
             wg_jobs[base + it.second].push_back(j);
-            it.first += (double)n[i] * (double)n[i];
+            it.first += cost[i];
             heap.push(it);
         }
     }
@@ -141,15 +154,17 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     }
     std::vector<int64_t> ns(count);
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
-    Plan plan = make_plan(ns, capacity);
+    Plan plan = make_plan(ns, capacity, batched_waves(), batched_unroll(a_dtype),
+                          a_dtype == JACOBI_F32 ? 16 : 32);
 
-    // workspace: per system buf0, buf1 (n*kt) and diag (n), 256-byte aligned
+    // workspace: per system buf0, buf1 (kt x xld, transposed) and diag (n)
     std::vector<size_t> off(count);
     size_t ws = 0;
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    auto xld_of = [](int64_t n) { return (n + 31) / 32 * 32; };
     for (int i = 0; i < count; ++i) {
         off[i] = ws;
-        ws += 2 * align(sizeof(float) * items[i].n * kt) + align(sizeof(float) * items[i].n);
+        ws += 2 * align(sizeof(float) * xld_of(items[i].n) * kt) + align(sizeof(float) * items[i].n);
     }
     const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
     const size_t job_b = align(sizeof(BJob) * std::max<size_t>(1, plan.jobs.size()));
@@ -178,9 +193,11 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         S.X = (float*)it.X;
         S.ldx = it.ldx;
         S.X0 = (const float*)it.X0;
+        const size_t xb = align(sizeof(float) * xld_of(it.n) * kt);
         S.buf0 = (float*)base;
-        S.buf1 = (float*)(base + align(sizeof(float) * it.n * kt));
-        S.diag = (const float*)(base + 2 * align(sizeof(float) * it.n * kt));
+        S.buf1 = (float*)(base + xb);
+        S.xld = xld_of(it.n);
+        S.diag = (const float*)(base + 2 * xb);
         S.n = it.n;
         S.k = (int32_t)it.k;
         S.nwg = plan.nwg[i];
@@ -213,7 +230,6 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     ba.parts = d_parts;
     ba.max_nwg = plan.max_nwg;
     ba.count = count;
-    ba.chunk = batched_chunk(kt);
     int rate_khz = 100000;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess ||
         rate_khz <= 0)

@@ -8,9 +8,11 @@
 //   * a wave owns a 16-row tile; lane l loads row (l % 16) and 16 bytes of
 //     consecutive columns (4 FP32 or 8 BF16 values) at column group l / 16,
 //     so one 16-byte load per lane feeds 4 (FP32) or 8 (BF16) MFMA k-steps;
-//   * the iterate chunk x[c0 .. c0+CH) is staged in LDS transposed (column c
-//     of X is an LDS row), so the matching B operand of 4 k-steps is one
-//     16-byte LDS read;
+//   * the iterate is kept transposed in global memory (column c of X is a
+//     contiguous row of xld floats), so the matching B operand of 4 k-steps
+//     is one 16-byte load that hits L1/L2 (X is small and every tile of the
+//     system reads it); no LDS staging and no barrier inside a sweep: the
+//     waves of a workgroup stream their 16-row tiles independently;
 //   * the diagonal term is masked in the A operand (sum over j != i);
 //   * the accumulator tile is the epilogue's input: division by a_ii, the
 //     distance max|x_new - x_old| (or its Euclidean form) and the stop test.
@@ -88,10 +90,16 @@ __device__ __forceinline__ uint64_t wmax(uint64_t v) {
 
 }  // namespace
 
+// x rows staged in LDS per chunk: 64 KiB of FP32 for the chunk.
+template <int KT>
+constexpr int batched_chunk_cols() {
+    return KT <= 16 ? 1024 : 512;
+}
+
 // ---------------------------------------------------------------------------
 // Setup: per system, gather alpha_ii, validate (zero / non-finite diagonal,
-// non-finite B or X0), copy X0 (or zeros) into buf0 with zero padding
-// columns, clear buf1.  grid = (row blocks, systems).
+// non-finite B or X0), write X0 (or zeros) transposed into buf0 and clear
+// buf1, padding included.  grid = (row blocks, systems).
 template <typename TA>
 __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict__ st, int kt) {
     const BSys S = sys[blockIdx.y];
@@ -99,7 +107,14 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
     const TA* A = reinterpret_cast<const TA*>(S.A);
     float* diag = const_cast<float*>(S.diag);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += stride) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.xld; i += stride) {
+        if (i >= S.n) {
+            for (int c = 0; c < kt; ++c) {
+                S.buf0[c * S.xld + i] = 0.0f;
+                S.buf1[c * S.xld + i] = 0.0f;
+            }
+            continue;
+        }
         const float d = widen1<TA>(A[i * S.lda + i]);
         diag[i] = d;
         if (d == 0.0f)
@@ -115,8 +130,8 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
                 const float b = S.B[i * S.ldb + c];
                 if (!isfinite(b) || !isfinite(x0)) bad = true;
             }
-            S.buf0[i * kt + c] = x0;
-            S.buf1[i * kt + c] = 0.0f;
+            S.buf0[c * S.xld + i] = x0;
+            S.buf1[c * S.xld + i] = 0.0f;
         }
         if (bad)
             __hip_atomic_fetch_min(&T->bad_rhs, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -125,19 +140,24 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
-template <typename TA, int KT, int W, int U>
-__global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
+//   W   waves per workgroup
+//   TPW 16-row tiles per wave in one pass (they share every B operand read)
+//   U   A blocks per pipeline stage (two stages in flight)
+template <typename TA, int KT, int W, int TPW, int U>
+__global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
     constexpr int VEC = 16 / (int)sizeof(TA);  // A values per 16-byte lane load
     constexpr int BW = 4 * VEC;                // columns of one A block (16 or 32)
     constexpr int NT = KT / 16;                // 16-column output tiles
     constexpr int NS = VEC / 4;                // 4-step MFMA groups per block
-    extern __shared__ __attribute__((aligned(16))) float xsT[];  // [KT][CH + 4]
+    constexpr int CH = batched_chunk_cols<KT>();  // x rows staged per chunk
+    constexpr int CHP = CH + 4;                // padded LDS row (bank spread)
+    static_assert(CH % (BW * U) == 0, "a pipeline stage never straddles chunks");
+    extern __shared__ __attribute__((aligned(16))) float xsT[];  // [KT][CHP]
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ uint32_t s_flag;
     __shared__ double s_delta;
 
-    const int CH = p.chunk, CHP = p.chunk + 4;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane >> 4, li = lane & 15;
 
@@ -152,8 +172,12 @@ __global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
             continue;  // invalid input: no sweep runs, X untouched
         const TA* A = reinterpret_cast<const TA*>(S.A);
         const int64_t n = S.n;
+        const int64_t xld = S.xld;
         const int k = S.k;
         const bool split = S.nwg > 1;
+        const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
+        const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks fully inside n
+        const int64_t nfull = (nbf / U) * U;           // blocks handled by the pipeline
         const float* xfinal = S.buf0;
         int32_t final_k = 0;
         uint32_t final_stop = STOP_RUNNING;
@@ -165,114 +189,155 @@ __global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
             float* xout = (sweep & 1) ? S.buf1 : S.buf0;
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * W) {
-                const int64_t rt = pr + 16 * wave;
-                const bool has_tile = rt < job.r1;
-                const int64_t arow_i = (rt + li) < n ? (rt + li) : (n - 1);
-                const TA* arow = A + arow_i * S.lda + VEC * grp;
-                f32x4 acc[NT];
+            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * W * TPW) {
+                int64_t rt[TPW];
+                const TA* arow[TPW];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                for (int64_t c0 = 0; c0 < n; c0 += CH) {
-                    const int cl = (int)((n - c0) < CH ? (n - c0) : CH);
-                    const int clp = (cl + BW - 1) / BW * BW;
+                for (int q = 0; q < TPW; ++q) {
+                    rt[q] = pr + 16 * (wave + W * q);
+                    int64_t ri = rt[q] + li;
+                    if (rt[q] >= job.r1) ri = job.r0;  // idle tile: load a valid row, discard
+                    if (ri >= n) ri = n - 1;
+                    arow[q] = A + ri * S.lda + VEC * grp;
+                }
+                f32x4 acc[TPW][NT];
+#pragma unroll
+                for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[q][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+                // x chunk staging: X is stored transposed, so a chunk is KT
+                // contiguous row pieces (zero padded past n in global memory).
+                int64_t cur_chunk = -1;
+                auto ensure_chunk = [&](int64_t b) {
+                    const int64_t ch = (b * BW) / CH;
+                    if (ch == cur_chunk) return;
+                    const int64_t c0 = ch * CH;
+                    const int64_t cl = (n - c0) < CH ? (n - c0) : CH;
+                    const int64_t clp = (cl + BW - 1) / BW * BW;
+                    const int nq = (int)(clp / 4);
                     __syncthreads();
-                    // stage x[c0 .. c0+cl) transposed, zero padded to clp
-                    {
-                        const float4* src = reinterpret_cast<const float4*>(xin + c0 * KT);
-                        const int nv = cl * KT / 4;
-                        for (int e4 = tid; e4 < nv; e4 += W * 64) {
-                            const float4 v = src[e4];
-                            const int j = (e4 * 4) / KT;
-                            const int c = (e4 * 4) % KT;
-                            xsT[(c + 0) * CHP + j] = v.x;
-                            xsT[(c + 1) * CHP + j] = v.y;
-                            xsT[(c + 2) * CHP + j] = v.z;
-                            xsT[(c + 3) * CHP + j] = v.w;
-                        }
-                        for (int e = tid; e < (clp - cl) * KT; e += W * 64) {
-                            const int j = cl + e / KT;
-                            const int c = e % KT;
-                            xsT[c * CHP + j] = 0.0f;
-                        }
+                    for (int e = tid; e < KT * nq; e += W * 64) {
+                        const int c = e / nq, j4 = e - c * nq;
+                        *reinterpret_cast<f32x4*>(xsT + c * CHP + 4 * j4) =
+                            *reinterpret_cast<const f32x4*>(xin + (int64_t)c * xld + c0 + 4 * j4);
                     }
                     __syncthreads();
-                    if (!has_tile) continue;
-                    const int nb = clp / BW;
-                    const int nbf = S.aligned ? (int)((n - c0 >= (int64_t)clp) ? nb : cl / BW) : 0;
-                    const bool dchunk = (c0 < rt + 16) && (rt < c0 + cl);
-                    auto mfma_block = [&](const float* a, int b) {
-                        const int jrel = b * BW;
-                        const int64_t colbase = c0 + jrel + VEC * grp;
-                        float av[VEC];
+                    cur_chunk = ch;
+                };
+                // MFMAs of one A block (TPW tiles share the B operand).
+                auto mfma_block = [&](float (&a)[TPW][VEC], int64_t b) {
+                    const int jrel = (int)(b * BW - cur_chunk * CH);
+                    f32x4 bx[NT][NS];
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) av[e] = a[e];
-                        if (dchunk && c0 + jrel < rt + 16 && rt < c0 + jrel + BW) {
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int sg = 0; sg < NS; ++sg)
+                            bx[t][sg] = *reinterpret_cast<const f32x4*>(
+                                xsT + (t * 16 + li) * CHP + jrel + VEC * grp + 4 * sg);
+                    const int64_t colbase = b * BW + VEC * grp;
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q) {
+                        if (b * BW < rt[q] + 16 && rt[q] < b * BW + BW) {
 #pragma unroll
                             for (int e = 0; e < VEC; ++e)
-                                if (colbase + e == rt + li) av[e] = 0.0f;
+                                if (colbase + e == rt[q] + li) a[q][e] = 0.0f;
                         }
 #pragma unroll
-                        for (int s = 0; s < NS; ++s) {
+                        for (int sg = 0; sg < NS; ++sg)
 #pragma unroll
-                            for (int t = 0; t < NT; ++t) {
-                                const f32x4 bv = *reinterpret_cast<const f32x4*>(
-                                    xsT + (t * 16 + li) * CHP + jrel + VEC * grp + 4 * s);
+                            for (int t = 0; t < NT; ++t)
 #pragma unroll
-                                for (int q = 0; q < 4; ++q)
-                                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                        av[4 * s + q], bv[q], acc[t], 0, 0, 0);
-                            }
-                        }
-                    };
-                    int b0 = 0;
-                    for (; b0 + U <= nbf; b0 += U) {
-                        u32x4 v[U];
+                                for (int r = 0; r < 4; ++r)
+                                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        a[q][4 * sg + r], bx[t][sg][r], acc[q][t], 0, 0, 0);
+                    }
+                };
+                // Full blocks: two pipeline stages of U blocks; the A loads of
+                // the next stage are in flight during the MFMAs (and the chunk
+                // staging) of the current one.
+                if (nfull > 0) {
+                    u32x4 v0[U][TPW], v1[U][TPW];
+                    auto issue = [&](u32x4 (&v)[U][TPW], int64_t bb) {
 #pragma unroll
                         for (int u = 0; u < U; ++u)
-                            v[u] = __builtin_nontemporal_load(
-                                reinterpret_cast<const u32x4*>(arow + c0 + (b0 + u) * BW));
+#pragma unroll
+                            for (int q = 0; q < TPW; ++q)
+                                v[u][q] = __builtin_nontemporal_load(
+                                    reinterpret_cast<const u32x4*>(arow[q] + (bb + u) * BW));
+                    };
+                    auto consume = [&](u32x4 (&v)[U][TPW], int64_t bb) {
+                        ensure_chunk(bb);
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
-                            float a[VEC];
-                            unpack<TA>(v[u], a);
-                            mfma_block(a, b0 + u);
+                            float a[TPW][VEC];
+#pragma unroll
+                            for (int q = 0; q < TPW; ++q) unpack<TA>(v[u][q], a[q]);
+                            mfma_block(a, bb + u);
                         }
+                    };
+                    issue(v0, 0);
+                    int64_t b0 = 0;
+                    for (; b0 + 2 * U <= nfull; b0 += 2 * U) {
+                        issue(v1, b0 + U);
+                        consume(v0, b0);
+                        if (b0 + 2 * U < nfull) issue(v0, b0 + 2 * U);
+                        consume(v1, b0 + U);
                     }
-                    for (; b0 < nb; ++b0) {
-                        float a[VEC];
-                        if (b0 < nbf) {
+                    if (b0 < nfull) consume(v0, b0);
+                }
+                // Remaining blocks (ragged tail, or every block of unaligned rows).
+                for (int64_t b = nfull; b < nb; ++b) {
+                    ensure_chunk(b);
+                    float a[TPW][VEC];
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q) {
+                        if (b < nbf) {
                             const u32x4 v = __builtin_nontemporal_load(
-                                reinterpret_cast<const u32x4*>(arow + c0 + b0 * BW));
-                            unpack<TA>(v, a);
+                                reinterpret_cast<const u32x4*>(arow[q] + b * BW));
+                            unpack<TA>(v, a[q]);
                         } else {
 #pragma unroll
                             for (int e = 0; e < VEC; ++e) {
-                                const int64_t col = c0 + b0 * BW + VEC * grp + e;
-                                a[e] = col < n ? widen1<TA>(arow[c0 + b0 * BW + e]) : 0.0f;
+                                const int64_t col = b * BW + VEC * grp + e;
+                                a[q][e] = col < n ? widen1<TA>(arow[q][b * BW + e]) : 0.0f;
                             }
                         }
-                        mfma_block(a, b0);
                     }
+                    mfma_block(a, b);
                 }
-                if (has_tile) {
+                // epilogue: lane holds rows rt + 4*grp + v, column t*16 + li
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    if (rt[q] >= job.r1) continue;
+                    const int64_t i0 = rt[q] + 4 * grp;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
+                        const int c = t * 16 + li;
+                        const f32x4 xo4 =
+                            *reinterpret_cast<const f32x4*>(xin + (int64_t)c * xld + i0);
+                        f32x4 xn4 = xo4;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int64_t i = rt + 4 * grp + v;
-                            const int c = t * 16 + li;
+                            const int64_t i = i0 + v;
                             if (i < job.r1 && c < k) {
-                                const float s = acc[t][v];
-                                const float xn = (S.B[i * S.ldb + c] - s) / S.diag[i];
-                                const float xo = xin[i * KT + c];
-                                xout[i * KT + c] = xn;
-                                const double dd = fabs((double)xn - (double)xo);
+                                const float xn = (S.B[i * S.ldb + c] - acc[q][t][v]) / S.diag[i];
+                                xn4[v] = xn;
+                                const double dd = fabs((double)xn - (double)xo4[v]);
                                 const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
                                 dmax = db > dmax ? db : dmax;
                                 xmax = mb > xmax ? mb : xmax;
                                 sq += dd * dd;
                             }
+                        }
+                        // rows past r1 keep their value (zero padding or another
+                        // workgroup's rows)
+                        if (i0 + 3 < job.r1) {
+                            *reinterpret_cast<f32x4*>(xout + (int64_t)c * xld + i0) = xn4;
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (i0 + v < job.r1) xout[(int64_t)c * xld + i0 + v] = xn4[v];
                         }
                     }
                 }
@@ -281,7 +346,6 @@ __global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
             dmax = wmax(dmax);
             xmax = wmax(xmax);
             sq = wsum(sq);
-            __syncthreads();
             if (lane == 0) {
                 red_d[wave] = dmax;
                 red_m[wave] = xmax;
@@ -368,26 +432,26 @@ __global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
         }
         if (failed) continue;
         // Copy this workgroup's rows of the final iterate to the caller's X.
-        // In the last sweep every element was written by the thread that
-        // copies it here, so no further synchronisation is needed.
+        // In the last sweep each element was written by the thread that copies
+        // it here (same tile walk), so no further synchronisation is needed.
         if (final_k > 0) {
-            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * W) {
-                const int64_t rt = pr + 16 * wave;
-                if (rt >= job.r1) continue;
+            for (int64_t rt = job.r0 + 16 * wave; rt < job.r1; rt += 16 * W) {
+                // same (row, column) -> thread map as the epilogue: tile
+                // pr + 16*(wave + W*q) is walked by this wave for every pass
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int64_t i = rt + 4 * grp + v;
                         const int c = t * 16 + li;
-                        if (i < job.r1 && c < k) S.X[i * S.ldx + c] = xfinal[i * KT + c];
+                        if (i < job.r1 && c < k) S.X[i * S.ldx + c] = xfinal[(int64_t)c * xld + i];
                     }
             }
         } else {
             for (int64_t e = tid; e < (job.r1 - job.r0) * k; e += W * 64) {
                 const int64_t i = job.r0 + e / k;
                 const int c = (int)(e % k);
-                S.X[i * S.ldx + c] = S.buf0[i * KT + c];
+                S.X[i * S.ldx + c] = S.buf0[(int64_t)c * xld + i];
             }
         }
         if (tid == 0 && job.rank == 0) {
@@ -401,16 +465,21 @@ __global__ __launch_bounds__(W * 64) void k_batched(BatchArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kBW = 8;   // waves per workgroup
-constexpr int kBU = 2;   // A blocks in flight per wave
+constexpr int kBW = 4;   // waves per workgroup
+constexpr int kTPW = 2;  // 16-row tiles per wave per pass
+constexpr int kBU = 2;   // A blocks per pipeline stage
 
-int batched_chunk(int32_t kt) { return kt <= 16 ? 1024 : 512; }
+int batched_waves() { return kBW * kTPW; }  // 16-row tiles per workgroup pass
+int batched_unroll(int32_t) { return 2 * kBU; }
 
-static size_t batched_lds(int32_t kt) { return (size_t)kt * (batched_chunk(kt) + 4) * sizeof(float); }
+static size_t batched_lds(int32_t kt) {
+    return (size_t)kt * ((kt <= 16 ? batched_chunk_cols<16>() : batched_chunk_cols<32>()) + 4) *
+           sizeof(float);
+}
 
 template <typename TA, int KT>
 static const void* batched_fn() {
-    return (const void*)k_batched<TA, KT, kBW, kBU>;
+    return (const void*)k_batched<TA, KT, kBW, kTPW, kBU>;
 }
 
 static const void* pick(int32_t a_dtype, int32_t kt) {
@@ -433,7 +502,7 @@ int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus) {
 
 hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,
                                 int32_t count, int64_t max_n, hipStream_t s) {
-    int64_t bx = (max_n + 255) / 256;
+    int64_t bx = (max_n + 32 + 255) / 256;
     if (bx > 64) bx = 64;
     if (a_dtype == 1)
         hipLaunchKernelGGL((k_batched_setup<float>), dim3((unsigned)bx, count), dim3(256), 0, s,

@@ -113,8 +113,8 @@ hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t 
 // Batched persistent sweeps (MFMA tiles), one launch for many systems.
 
 // Per-system descriptor (device copy).  A is FP32 or BF16 (the launch's
-// dtype); B, X and the iterate buffers are FP32.  Iterate buffers have
-// leading dimension kt (16 or 32) with zero padding columns.
+// dtype); B, X and the iterate buffers are FP32.  The iterate buffers hold X
+// transposed: kt rows (16 or 32) of xld >= n floats, padding zero.
 struct BSys {
     const void* A;
     int64_t lda;
@@ -123,8 +123,9 @@ struct BSys {
     float* X;          // caller's output (ldx), written once at the end
     int64_t ldx;
     const float* X0;   // caller's initial approximation (ldx), or null for zero
-    float* buf0;       // x^(0) on entry; ping-pong with buf1
+    float* buf0;       // x^(0) on entry (transposed); ping-pong with buf1
     float* buf1;
+    int64_t xld;       // leading dimension of the transposed iterate (multiple of 32)
     const float* diag;
     int64_t n;
     int32_t k;
@@ -166,7 +167,6 @@ struct BatchArgs {
     double* parts;            // [2][count][max_nwg] L2 partial sums
     int32_t max_nwg;
     int32_t count;
-    int32_t chunk;            // x rows staged in LDS per chunk (multiple of 32)
     int64_t spin_limit;       // wall-clock ticks (100 MHz) before a barrier wait gives up
 };
 
@@ -175,7 +175,8 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
 hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int grid,
                           hipStream_t s);
 int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus);
-int batched_chunk(int32_t kt);
+int batched_waves();
+int batched_unroll(int32_t a_dtype);
 
 // Default launch configuration for a sweep of this shape.
 LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus);

@@ -35,7 +35,7 @@ def test_refine_parity(jac, lo, n, k):
     say("refine", lo, n, k)
     X, info = jac.solve(dev(A), dev(B), mode="refine", sweep_dtype=lo)
     assert info["status"] == jac.OK, info
-    assert info["rel_residual"] < 1e-11
+    assert info["rel_residual"] < 1e-12
     assert info["outer_iterations"] >= 2
     assert rel_err(host(X), xr) <= REL_REFINE
     R = oracle.residual(A, B, host(X))
@@ -63,9 +63,10 @@ def test_refine_caps_and_x0(jac):
 def test_c4_full_size(jac):
     """n = 32768, FP64 A stored BF16 for the sweeps (2 GiB) with the FP64 A
     (8 GiB) kept on the device for the residual.  The configuration's stop
-    rule ||r||/||b|| < 1e-10 bounds the error only up to cond(A), so the
-    default residual target is 1e-11; the residual is recomputed by the oracle
-    and x is compared with x_ref at the 1e-10 bar."""
+    rule ||r||_2/||b||_2 < 1e-10 leaves a max-norm error of 1.5e-10 on this
+    system (measured: the error/residual ratio is about 15), so the default
+    residual target is 1e-12; the residual is recomputed by the oracle and x is
+    compared with x_ref at the 1e-10 bar."""
     import torch
     A, Xt, B = synth.c4()
     b = B[:, 0]
