@@ -18,6 +18,11 @@ The other configurations (--config) are measured with the same JSON layout:
       batched MFMA launch per step (GB/s of A streamed and MFMA TF/s)
   c4  n = 32768 FP64 system, BF16 sweeps inside FP64 iterative refinement:
       time to ||r||/||b|| below target, bytes of all passes
+  c5  serving: 2000 FP64 requests (n log-uniform in [256, 16384], k in
+      {1, 4, 16}, FP32/BF16 inner sweeps) cycling through a pool of seeded
+      systems in pinned host memory: saturation solves/s, p50/p99 latency at
+      a Poisson rate of 0.7x capacity, and the plain per-request solver (FIFO
+      jacobi_solve with host copies) on the same requests
 
 Prints one JSON line.  value = algorithmic bytes moved by all sweeps of all
 timed steps / wall time of the timed region (GB/s); the roofline object uses
@@ -75,7 +80,9 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-events", action="store_true")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--pool", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -91,7 +98,7 @@ def main() -> int:
     import synth
 
     if args.config != "c2":
-        res = {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4}[args.config](args)
+        res = {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.config](args)
         print(json.dumps(res), flush=True)
         return 0
 
@@ -347,6 +354,95 @@ def bench_c4(args):
                        "traffic": None, "kernel": "whole refinement call (residual + sweeps)"}
     res["cpu_baseline"] = None
     ctx.close()
+    return res
+
+
+def bench_c5(args):
+    """Serving: continuous batching vs the plain per-request solver."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1403_5805_amd as jac
+    import synth
+    spec = synth.c5_requests(args.requests)
+    P = min(args.pool, len(spec))
+    pool = []
+    for i in range(P):
+        n, k, lo = spec[i]
+        At = torch.empty((n, n), dtype=torch.float64).pin_memory()
+        A, Xt, B = synth.c5_system(i, n, k, out=At.numpy())
+        pool.append((At, A, np.ascontiguousarray(B), lo, Xt))
+    reqs = [pool[i % P] for i in range(len(spec))]
+    R = len(reqs)
+    rel_tol = 1e-12
+
+    def run_server(arrivals=None):
+        srv = jac.Server(max_active=64)
+        outs = [np.empty(r[2].shape) for r in reqs]
+        t0 = time.perf_counter()
+        tickets = []
+        for i, r in enumerate(reqs):
+            if arrivals is not None:
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            t, st = srv.submit(r[1], r[2], out=outs[i], sweep_dtype=r[3], rel_tol=rel_tol)
+            tickets.append(t)
+        infos = [srv.wait(t)[1] for t in tickets]
+        el = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return el, st, infos, outs
+
+    el_sat, st_sat, infos_sat, outs_sat = run_server()
+    ok = sum(1 for i in infos_sat if i["status"] == jac.OK)
+    cap = R / el_sat
+    rate = 0.7 * cap
+    arr = synth.poisson_arrivals(R, rate, synth.seed_for(4) + 5)
+    el_poi, st_poi, infos_poi, outs_poi = run_server(arr)
+    same = all(np.array_equal(a, b) for a, b in zip(outs_sat, outs_poi))
+    # plain per-request solver: copy in, jacobi_solve (refine), copy out, FIFO
+    ctx = jac.Context(0)
+    t0 = time.perf_counter()
+    base_ok = 0
+    for r in reqs:
+        Ad = r[0].to("cuda", non_blocking=True)
+        Bd = torch.from_numpy(r[2]).to("cuda")
+        X, info = jac.solve(Ad, Bd, ctx=ctx, mode="refine", sweep_dtype=r[3], refine_tol=rel_tol)
+        X.cpu()
+        base_ok += info["status"] == jac.OK
+        del Ad
+    el_base = time.perf_counter() - t0
+    ctx.close()
+    # accuracy on the small pool systems against the oracle's tight solution
+    errs = []
+    for i in range(P):
+        At, A, B, lo, Xt = pool[i]
+        if A.shape[0] <= 1500:
+            xr, _ = oracle.jacobi(A, B, tol=1e-15, max_iter=1000)
+            errs.append(float(np.abs(outs_sat[i] - xr).max() / np.abs(xr).max()))
+    res = _common(args, "served solves/s (2000 Poisson requests, n 256-16384, k 1/4/16, "
+                  "FP32/BF16 sweeps + FP64 refinement)", round(R / el_sat, 1), "solves/s",
+                  round(el_sat * 1e3 / R, 3), "f32/bf16+f64",
+                  {"workload": "serving: FP64 requests, n log-uniform [256,16384], k in "
+                               "{1,4,16}, margin U[0.2,1]*rowsum, rel tol 1e-12",
+                   "requests": R, "distinct_systems": P})
+    res["steps"] = R
+    res["all_ok"] = ok == R
+    res["saturation"] = {"solves_per_s": round(R / el_sat, 2), "p50_ms": st_sat["p50_ms"],
+                         "p99_ms": st_sat["p99_ms"], "hbm_peak_GB": st_sat["hbm_peak"] / 1e9,
+                         "steps": st_sat["steps"]}
+    res["poisson"] = {"rate_per_s": round(rate, 2), "solves_per_s": round(R / el_poi, 2),
+                      "p50_ms": st_poi["p50_ms"], "p99_ms": st_poi["p99_ms"],
+                      "p50_device_ms": st_poi["p50_device_ms"],
+                      "p99_device_ms": st_poi["p99_device_ms"]}
+    res["results_same_under_both_schedules"] = same
+    res["plain_per_request"] = {"solves_per_s": round(R / el_base, 2), "ok": int(base_ok)}
+    res["speedup_vs_plain"] = round((R / el_sat) / (R / el_base), 3)
+    res["max_rel_err_vs_oracle_small"] = max(errs) if errs else None
+    res["roofline"] = None
+    res["cpu_baseline"] = None
     return res
 
 

@@ -178,6 +178,82 @@ jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count, const jacobi_
                                    int32_t a_dtype, const jacobi_options* opt, hipStream_t stream,
                                    jacobi_info* infos);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop that solves FP64 systems as they arrive, with
+ * continuous batching.  Each request is solved by iterative refinement (the
+ * REFINE mode above): FP64 residual on the device, inner Jacobi sweeps on a
+ * reduced-precision copy of A.  A worker thread admits queued requests while
+ * their device footprint fits the HBM budget and an active slot is free,
+ * copies A and B to the device on a copy stream (overlapping the sweeps of
+ * requests already admitted), and steps all active requests together: one
+ * step = one FP64 residual pass per request, then one persistent batched
+ * launch running every request's inner solve.  Requests that meet their
+ * tolerance (or fail) are copied back and retired at once, freeing memory for
+ * the next ones.  A request's result does not depend on the other requests in
+ * flight (bitwise the same alone and in the mix). */
+
+typedef struct {
+    int32_t device;            /* HIP device                                                  */
+    int32_t max_active;        /* requests stepped together (default 64)                      */
+    uint64_t hbm_budget_bytes; /* device memory for request state, 0 = 80% of free memory     */
+    int32_t inner_max;         /* inner sweep cap per refinement step (default 64)            */
+    int32_t max_outer;         /* refinement steps per request (default 50)                   */
+    double inner_rel_tol;      /* inner relative stop (default 1e-3)                          */
+} jacobi_serve_config;
+
+typedef struct {
+    int64_t n, k;              /* size, right-hand sides (k <= 32)                            */
+    const double* A;           /* HOST n x n FP64, leading dimension lda (pinned is faster)   */
+    int64_t lda;
+    const double* B;           /* HOST n x k FP64, leading dimension ldb                      */
+    int64_t ldb;
+    double* X;                 /* HOST n x k FP64 output, leading dimension ldx               */
+    int64_t ldx;
+    int32_t sweep_dtype;       /* JACOBI_F32 or JACOBI_BF16 inner sweeps                      */
+    int32_t reserved;
+    double rel_tol;            /* stop when ||r||_2 < rel_tol * ||B||_2                       */
+} jacobi_request;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, failed, active, queued;
+    uint64_t hbm_in_use, hbm_peak, steps;
+    double solves_per_s;       /* completed / (last completion - first submission)           */
+    double p50_ms, p99_ms;     /* end-to-end latency: submission -> result in host memory    */
+    double p50_device_ms, p99_device_ms; /* data on the device -> result ready on the device  */
+    double elapsed_s;
+} jacobi_serve_stats;
+
+typedef struct jacobi_server jacobi_server;
+
+/* Fill *cfg with the defaults above. */
+void jacobi_serve_config_default(jacobi_serve_config* cfg);
+
+/* Start a server (its worker thread, streams and context) on cfg->device. */
+jacobi_status jacobi_serve_create(const jacobi_serve_config* cfg, jacobi_server** out);
+
+/* Queue a request; returns at once with a ticket.  The caller keeps req->A,
+ * req->B and req->X alive and unchanged until the ticket completes.  A request
+ * whose footprint can never fit the budget returns JACOBI_ERR_REJECTED (and a
+ * ticket that polls as rejected); bad sizes return JACOBI_ERR_INVALID_ARG. */
+jacobi_status jacobi_serve_submit(jacobi_server* srv, const jacobi_request* req,
+                                  uint64_t* ticket);
+
+/* Outcome of a ticket: JACOBI_PENDING while queued or running, else its final
+ * status (info filled: iterations = inner sweeps, outer_iterations,
+ * rel_residual, device_ms = device latency). */
+jacobi_status jacobi_serve_poll(jacobi_server* srv, uint64_t ticket, jacobi_info* info);
+
+/* Block until the ticket completes or timeout_us passes (< 0: no timeout);
+ * returns JACOBI_PENDING on timeout. */
+jacobi_status jacobi_serve_wait(jacobi_server* srv, uint64_t ticket, int64_t timeout_us,
+                                jacobi_info* info);
+
+jacobi_status jacobi_serve_stats_get(jacobi_server* srv, jacobi_serve_stats* stats);
+
+/* Stop the worker; requests not finished complete as JACOBI_CANCELLED (their X
+ * untouched).  Frees every device buffer of the server. */
+jacobi_status jacobi_serve_destroy(jacobi_server* srv);
+
 /* Human-readable name of a status code (static string). */
 const char* jacobi_status_string(int32_t status);
 

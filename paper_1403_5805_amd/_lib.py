@@ -89,8 +89,9 @@ class ServeConfig(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("max_active", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_uint64),
-        ("sweeps_per_step", ctypes.c_int32),
-        ("copy_streams", ctypes.c_int32),
+        ("inner_max", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32),
+        ("inner_rel_tol", ctypes.c_double),
     ]
 
 
@@ -105,11 +106,8 @@ class Request(ctypes.Structure):
         ("X", ctypes.c_void_p),
         ("ldx", ctypes.c_int64),
         ("sweep_dtype", ctypes.c_int32),
-        ("max_outer", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("rel_tol", ctypes.c_double),
-        ("inner_rel_tol", ctypes.c_double),
-        ("max_inner", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
     ]
 
 
@@ -118,6 +116,7 @@ class ServeStats(ctypes.Structure):
         ("submitted", ctypes.c_uint64),
         ("completed", ctypes.c_uint64),
         ("rejected", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
         ("active", ctypes.c_uint64),
         ("queued", ctypes.c_uint64),
         ("hbm_in_use", ctypes.c_uint64),
@@ -130,6 +129,9 @@ class ServeStats(ctypes.Structure):
         ("p99_device_ms", ctypes.c_double),
         ("elapsed_s", ctypes.c_double),
     ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -164,6 +166,8 @@ def load():
         lib.jacobi_solve_batched.argtypes = [vp, i32, ctypes.POINTER(System), i32,
                                              ctypes.POINTER(Options), vp, ctypes.POINTER(Info)]
     if hasattr(lib, "jacobi_serve_create"):
+        lib.jacobi_serve_config_default.restype = None
+        lib.jacobi_serve_config_default.argtypes = [ctypes.POINTER(ServeConfig)]
         lib.jacobi_serve_create.restype = i32
         lib.jacobi_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
         lib.jacobi_serve_submit.restype = i32

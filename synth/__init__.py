@@ -80,11 +80,13 @@ def _fp(a):
 
 
 def dominant(n: int, k: int = 1, seed: int = SEED_BASE, mode: int = ADDITIVE,
-             lo: float = 1.0, hi: float = 2.0, lda: int | None = None):
-    """FP64 diagonally dominant system.  Returns (A[n, lda], X_true[n, k], B[n, k])."""
+             lo: float = 1.0, hi: float = 2.0, lda: int | None = None, out=None):
+    """FP64 diagonally dominant system.  Returns (A[n, lda], X_true[n, k], B[n, k]).
+    `out` may supply the (n, lda) float64 array for A (e.g. pinned memory)."""
     lib = load()
     lda = lda or n
-    A = np.zeros((n, lda), dtype=np.float64)
+    A = out if out is not None else np.zeros((n, lda), dtype=np.float64)
+    assert A.shape == (n, lda) and A.dtype == np.float64 and A.flags.c_contiguous
     X = np.empty((n, k), dtype=np.float64)
     B = np.empty((n, k), dtype=np.float64)
     lib.synth_dominant(n, k, seed, mode, lo, hi, _dp(A), lda, _dp(X), _dp(B))
@@ -164,3 +166,22 @@ def c3_system(i: int, n: int, k: int = 32):
 def c4(n: int = 32768):
     """FP64 n=32768, multiplicative margin U[0.5,1] (swept in BF16)."""
     return dominant(n, 1, seed_for(3), MULTIPLICATIVE, 0.5, 1.0)
+
+
+C5_STREAM_K = 9
+C5_STREAM_DTYPE = 10
+
+
+def c5_requests(count: int = 2000):
+    """Serving workload: per request (n, k, sweep dtype); n log-uniform in
+    [256, 16384], k uniform over {1, 4, 16}, FP32 or BF16 inner sweeps 50/50."""
+    sd = seed_for(4)
+    ns = log_uniform_sizes(count, 256, 16384, sd)
+    ks = choice(sd, C5_STREAM_K, count, [1, 4, 16])
+    dts = choice(sd, C5_STREAM_DTYPE, count, ["f32", "bf16"])
+    return [(int(n), int(k), d) for n, k, d in zip(ns, ks, dts)]
+
+
+def c5_system(i: int, n: int, k: int, out=None):
+    """System for request i: multiplicative margin U[0.2,1]."""
+    return dominant(n, k, seed_for(4) * 1000003 + i, MULTIPLICATIVE, 0.2, 1.0, out=out)
