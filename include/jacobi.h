@@ -38,6 +38,9 @@ extern "C" {
 
 typedef struct ihipStream_t* hipStream_t;
 
+/* Entry points are the only symbols the shared library exports. */
+#define JACOBI_API __attribute__((visibility("default")))
+
 typedef enum {
     JACOBI_OK = 0,                   /* converged: distance < tol                      */
     JACOBI_NOT_CONVERGED = 1,        /* cap L reached (sec. 2, pseudocode step 3)      */
@@ -114,14 +117,14 @@ typedef struct jacobi_ctx jacobi_ctx;
 
 /* Fill *opt with the defaults above (the paper's experiment values tol = 1e-8
  * and L = 10000, sec. 4). */
-void jacobi_options_default(jacobi_options* opt);
+JACOBI_API void jacobi_options_default(jacobi_options* opt);
 
 /* Create a context bound to HIP device `device`: it owns device workspaces
  * (iterate ping-pong buffer, diagonal, stop-flag block) reused across calls.
  * Calls on one context are serialised by an internal lock.  Returns
  * JACOBI_ERR_INVALID_ARG for a bad device or NULL out. */
-jacobi_status jacobi_ctx_create(int32_t device, jacobi_ctx** out);
-jacobi_status jacobi_ctx_destroy(jacobi_ctx* ctx);
+JACOBI_API jacobi_status jacobi_ctx_create(int32_t device, jacobi_ctx** out);
+JACOBI_API jacobi_status jacobi_ctx_destroy(jacobi_ctx* ctx);
 
 /* Solve A X = B (sec. 2) for one dense system with k right-hand sides.
  *
@@ -143,10 +146,11 @@ jacobi_status jacobi_ctx_destroy(jacobi_ctx* ctx);
  * or an error.  On OK, X holds the iterate whose distance to its predecessor
  * met the test; on NOT_CONVERGED, X^(L); on DIVERGED, the last (non-finite)
  * iterate. */
-jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k, int32_t a_dtype,
-                           const void* A, int64_t lda, const void* B, int64_t ldb,
-                           const void* X0, void* X, int64_t ldx, const jacobi_options* opt,
-                           hipStream_t stream, jacobi_info* info);
+JACOBI_API jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k,
+                                      int32_t a_dtype, const void* A, int64_t lda,
+                                      const void* B, int64_t ldb, const void* X0, void* X,
+                                      int64_t ldx, const jacobi_options* opt,
+                                      hipStream_t stream, jacobi_info* info);
 
 /* One system of a batch (device pointers; same conventions as jacobi_solve). */
 typedef struct {
@@ -174,9 +178,10 @@ typedef struct {
  * arguments gets JACOBI_ERR_INVALID_ARG and is skipped), or an error for the
  * whole call (bad options, device failure).  Results depend only on each
  * system's own data: a system gives bitwise the same X alone and in a batch. */
-jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count, const jacobi_system* systems,
-                                   int32_t a_dtype, const jacobi_options* opt, hipStream_t stream,
-                                   jacobi_info* infos);
+JACOBI_API jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count,
+                                              const jacobi_system* systems, int32_t a_dtype,
+                                              const jacobi_options* opt, hipStream_t stream,
+                                              jacobi_info* infos);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop that solves FP64 systems as they arrive, with
@@ -226,39 +231,39 @@ typedef struct {
 typedef struct jacobi_server jacobi_server;
 
 /* Fill *cfg with the defaults above. */
-void jacobi_serve_config_default(jacobi_serve_config* cfg);
+JACOBI_API void jacobi_serve_config_default(jacobi_serve_config* cfg);
 
 /* Start a server (its worker thread, streams and context) on cfg->device. */
-jacobi_status jacobi_serve_create(const jacobi_serve_config* cfg, jacobi_server** out);
+JACOBI_API jacobi_status jacobi_serve_create(const jacobi_serve_config* cfg, jacobi_server** out);
 
 /* Queue a request; returns at once with a ticket.  The caller keeps req->A,
  * req->B and req->X alive and unchanged until the ticket completes.  A request
  * whose footprint can never fit the budget returns JACOBI_ERR_REJECTED (and a
  * ticket that polls as rejected); bad sizes return JACOBI_ERR_INVALID_ARG. */
-jacobi_status jacobi_serve_submit(jacobi_server* srv, const jacobi_request* req,
-                                  uint64_t* ticket);
+JACOBI_API jacobi_status jacobi_serve_submit(jacobi_server* srv, const jacobi_request* req,
+                                             uint64_t* ticket);
 
 /* Outcome of a ticket: JACOBI_PENDING while queued or running, else its final
  * status (info filled: iterations = inner sweeps, outer_iterations,
  * rel_residual, device_ms = device latency). */
-jacobi_status jacobi_serve_poll(jacobi_server* srv, uint64_t ticket, jacobi_info* info);
+JACOBI_API jacobi_status jacobi_serve_poll(jacobi_server* srv, uint64_t ticket, jacobi_info* info);
 
 /* Block until the ticket completes or timeout_us passes (< 0: no timeout);
  * returns JACOBI_PENDING on timeout. */
-jacobi_status jacobi_serve_wait(jacobi_server* srv, uint64_t ticket, int64_t timeout_us,
-                                jacobi_info* info);
+JACOBI_API jacobi_status jacobi_serve_wait(jacobi_server* srv, uint64_t ticket,
+                                           int64_t timeout_us, jacobi_info* info);
 
-jacobi_status jacobi_serve_stats_get(jacobi_server* srv, jacobi_serve_stats* stats);
+JACOBI_API jacobi_status jacobi_serve_stats_get(jacobi_server* srv, jacobi_serve_stats* stats);
 
 /* Stop the worker; requests not finished complete as JACOBI_CANCELLED (their X
  * untouched).  Frees every device buffer of the server. */
-jacobi_status jacobi_serve_destroy(jacobi_server* srv);
+JACOBI_API jacobi_status jacobi_serve_destroy(jacobi_server* srv);
 
 /* Human-readable name of a status code (static string). */
-const char* jacobi_status_string(int32_t status);
+JACOBI_API const char* jacobi_status_string(int32_t status);
 
 /* Thread-local description of the last error raised in this thread ("" if none). */
-const char* jacobi_last_error(void);
+JACOBI_API const char* jacobi_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,29 @@ def _ld(t) -> int:
     return max(t.stride(0), t.shape[1])
 
 
+def _vec_dtype(a_dtype: int, mode: str = "plain"):
+    """Element type of B, x0 and X for a given A type (include/jacobi.h)."""
+    torch = _torch()
+    return torch.float64 if (a_dtype == F64 or mode in ("refine", 1)) else torch.float32
+
+
+def _check_operand(t, name: str, device, dtype, shape) -> None:
+    """Reject what would make the library read or write outside a tensor:
+    host tensors, another device, another element type or shape, and row
+    views whose rows overlap (row stride below the row length)."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, A is on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if t.dim() == 2 and t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name}: rows overlap (row stride {t.stride(0)} < {t.shape[1]})")
+    _ld(t)
+
+
 def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype="bf16",
                  inner_rel_tol=1e-3, max_inner=200, max_outer=50, refine_tol=1e-12,
                  sync_every=0, profile=False) -> Options:
@@ -134,17 +157,24 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
     n = A.shape[0]
     vec = B.dim() == 1
     k = 1 if vec else B.shape[1]
-    if B.shape[0] != n:
-        raise ValueError("B must have n rows")
+    if B.shape[0] != n or B.dim() > 2:
+        raise ValueError("B must be (n,) or (n, k)")
+    dt = _a_dtype(A)
+    _check_operand(A, "A", A.device, A.dtype, (n, n))
+    vdt = _vec_dtype(dt, opts.get("mode", "plain"))
+    _check_operand(B, "B", A.device, vdt, B.shape)
     if out is None:
         out = torch.empty((n,) if vec else (n, k), dtype=B.dtype, device=B.device)
+    _check_operand(out, "out", A.device, vdt, B.shape)
+    if x0 is not None:
+        _check_operand(x0, "x0", A.device, vdt, B.shape)
     if x0 is not None and not vec and _ld(x0) != _ld(out):
         x0 = x0.contiguous()
         if _ld(out) != k:
             raise ValueError("x0 and out must share a leading dimension")
     o = make_options(**opts)
     info = Info()
-    st = lib.jacobi_solve(ctx.handle if ctx else None, n, k, _a_dtype(A), _ptr(A), _ld(A),
+    st = lib.jacobi_solve(ctx.handle if ctx else None, n, k, dt, _ptr(A), _ld(A),
                           _ptr(B), _ld(B) if not vec else 1,
                           _ptr(x0) if x0 is not None else None, _ptr(out),
                           _ld(out) if not vec else 1, ctypes.byref(o),

@@ -16,7 +16,8 @@ def solve_batched(systems, *, outs=None, ctx=None, stream=None, tol=1e-8, max_it
     Returns (list of X, list of info dicts)."""
     import torch
 
-    from . import _a_dtype, _ld, _stream_handle, make_options, status_string
+    from . import (_a_dtype, _check_operand, _ld, _stream_handle, _vec_dtype, make_options,
+                   status_string)
     lib = _lib.load()
     count = len(systems)
     if count == 0:
@@ -33,9 +34,18 @@ def solve_batched(systems, *, outs=None, ctx=None, stream=None, tol=1e-8, max_it
         vec = B.dim() == 1
         n = A.shape[0]
         k = 1 if vec else B.shape[1]
+        dev = systems[0][0].device
+        vdt = _vec_dtype(dt)
+        if A.dim() != 2 or A.shape[0] != A.shape[1] or B.dim() > 2 or B.shape[0] != n:
+            raise ValueError(f"system {i}: A must be (n, n) and B (n,) or (n, k)")
+        _check_operand(A, f"A[{i}]", dev, A.dtype, (n, n))
+        _check_operand(B, f"B[{i}]", dev, vdt, B.shape)
         X = outs[i] if outs is not None else torch.empty_like(B)
-        if x0 is not None and _ld(x0) != _ld(X):
-            x0 = x0.contiguous()
+        _check_operand(X, f"out[{i}]", dev, vdt, B.shape)
+        if x0 is not None:
+            _check_operand(x0, f"x0[{i}]", dev, vdt, B.shape)
+            if _ld(x0) != _ld(X):
+                x0 = x0.contiguous()
         keep.append(x0)
         arr[i].n = n
         arr[i].k = k

@@ -21,11 +21,12 @@ BUILD = os.path.join(HERE, "_build")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("JACOBI_OFFLOAD_ARCH", "gfx950")
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 
-SOURCES = ["sweep.hip", "batched.hip", "api.cpp", "refine.cpp", "batch_api.cpp", "serve.cpp"]
+SOURCES = ["sweep.hip", "batched.hip", "api.cpp", "refine.cpp", "batch_api.cpp", "plan.cpp",
+           "serve.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "plan.h"
 
 namespace jac {
 
@@ -19,17 +20,6 @@ struct BatchItem {
     int64_t ldx;
     int32_t max_iter;
 };
-
-// Workgroup plan: jobs of workgroup g are jobs[job_off[g] .. job_off[g+1]).
-struct Plan {
-    std::vector<int> nwg;        // workgroups per system
-    std::vector<BJob> jobs;
-    std::vector<int32_t> job_off;
-    int grid = 0;
-    int max_nwg = 1;
-};
-
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw);
 
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
                           const jacobi_options& o, int32_t test, double rel, hipStream_t s,

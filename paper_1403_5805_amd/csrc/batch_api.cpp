@@ -30,111 +30,6 @@ static double bits_to_double(uint64_t b) {
     return d;
 }
 
-// Modelled time of one sweep of rows [0, rows) of an n-column system on one
-// workgroup: each wave walks ceil(tiles / W) 16-row tiles, each tile takes
-// ceil(blocks / U) load round trips plus its epilogue.  Units are arbitrary;
-// only ratios matter.
-static double job_cost(int64_t n, int64_t rows, int waves, int unroll, int bw) {
-    const double tiles_per_wave = std::ceil(std::ceil((double)rows / 16.0) / waves);
-    const double blocks = std::ceil((double)n / bw);
-    return tiles_per_wave * (1.0 + std::ceil(blocks / unroll)) + 1.0;
-}
-
-// Split big systems over several workgroups and pack small systems whole
-// into the remaining workgroups (longest-processing-time first), both by the
-// modelled sweep time above.  A workgroup that shares a system with others
-// owns nothing else, so barrier waits only involve workgroups that are certain
-// to arrive.
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw) {
-    Plan p;
-    const int count = (int)n.size();
-    p.nwg.assign(count, 1);
-    if (count == 0) {
-        p.job_off.push_back(0);
-        return p;
-    }
-    std::vector<double> cost(count);
-    double total = 0.0;
-    for (int i = 0; i < count; ++i) {
-        cost[i] = job_cost(n[i], n[i], waves, unroll, bw);
-        total += cost[i];
-    }
-    const double target = total / std::max(1, capacity);
-    std::vector<int> big, small;
-    int g_big = 0;
-    for (int i = 0; i < count; ++i) {
-        const int64_t tiles = (n[i] + 15) / 16;
-        int want = (int)std::lround(cost[i] / target);
-        want = (int)std::min<int64_t>(want, tiles);
-        if (want >= 2) {
-            p.nwg[i] = want;
-            big.push_back(i);
-            g_big += want;
-        } else {
-            small.push_back(i);
-        }
-    }
-    const int reserve = small.empty() ? 0 : std::max(1, std::min((int)small.size(), capacity / 8));
-    while (g_big > capacity - reserve && !big.empty()) {
-        // shrink the largest shares until the plan fits the resident grid
-        int best = big[0];
-        for (int i : big)
-            if (p.nwg[i] > p.nwg[best]) best = i;
-        p.nwg[best] -= 1;
-        g_big -= 1;
-        if (p.nwg[best] == 1) {
-            big.erase(std::find(big.begin(), big.end(), best));
-            small.push_back(best);
-            g_big -= 1;
-        }
-    }
-    std::vector<std::vector<BJob>> wg_jobs;
-    for (int i : big) {
-        const int64_t tiles = (n[i] + 15) / 16;
-        for (int r = 0; r < p.nwg[i]; ++r) {
-            const int64_t t0 = tiles * r / p.nwg[i], t1 = tiles * (r + 1) / p.nwg[i];
-            BJob j;
-            j.sys = i;
-            j.rank = r;
-            j.r0 = (int32_t)(16 * t0);
-            j.r1 = (int32_t)std::min<int64_t>(n[i], 16 * t1);
-            wg_jobs.push_back({j});
-        }
-    }
-    const int bins = std::max(small.empty() ? 0 : 1,
-                              std::min((int)small.size(), capacity - (int)wg_jobs.size()));
-    if (bins > 0) {
-        std::sort(small.begin(), small.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        using Item = std::pair<double, int>;
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-        const size_t base = wg_jobs.size();
-        wg_jobs.resize(base + bins);
-        for (int b = 0; b < bins; ++b) heap.push({0.0, b});
-        for (int i : small) {
-            Item it = heap.top();
-            heap.pop();
-            BJob j;
-            j.sys = i;
-            j.rank = 0;
-            j.r0 = 0;
-            j.r1 = (int32_t)n[i];
-            wg_jobs[base + it.second].push_back(j);
-            it.first += cost[i];
-            heap.push(it);
-        }
-    }
-    p.job_off.push_back(0);
-    for (auto& v : wg_jobs) {
-        if (v.empty()) continue;
-        for (auto& j : v) p.jobs.push_back(j);
-        p.job_off.push_back((int32_t)p.jobs.size());
-    }
-    p.grid = (int)p.job_off.size() - 1;
-    p.max_nwg = 1;
-    for (int v : p.nwg) p.max_nwg = std::max(p.max_nwg, v);
-    return p;
-}
-
 // Run the persistent MFMA kernel on `count` FP32/BF16 systems (k <= 32).
 // infos[i] receives each system's outcome.
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
@@ -156,6 +51,12 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
     Plan plan = make_plan(ns, capacity, batched_waves(), batched_unroll(a_dtype),
                           a_dtype == JACOBI_F32 ? 16 : 32);
+    if (plan.grid > capacity) {
+        // a cooperative launch needs every workgroup resident at once
+        set_error("batched plan of %d workgroups exceeds the resident grid %d", plan.grid,
+                  capacity);
+        return JACOBI_ERR_INTERNAL;
+    }
 
     // workspace: per system buf0, buf1 (kt x xld, transposed) and diag (n)
     std::vector<size_t> off(count);

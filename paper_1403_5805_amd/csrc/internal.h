@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "plan.h"
+
 namespace jac {
 
 // Stop codes written by the device into Ctl::stop.
@@ -149,14 +151,6 @@ struct alignas(64) BState {
     uint64_t final_delta;    // double bits
     int64_t bad_diag;        // validation: min over bad diagonals of 2*row + (non-finite ? 1 : 0)
     int64_t bad_rhs;         // validation: first row with a non-finite B or X0 entry
-};
-
-// One unit of work for a workgroup: rows [r0, r1) of system sys.
-struct BJob {
-    int32_t sys;
-    int32_t rank;   // index of this workgroup among the system's workgroups
-    int32_t r0;
-    int32_t r1;
 };
 
 struct BatchArgs {

@@ -46,15 +46,23 @@ class Server:
         """Queue A x = B (host float64 arrays, B (n,) or (n, k)).  Returns
         (ticket, status) where status is 0 when queued, else the error code."""
         A = np.ascontiguousarray(A, dtype=np.float64)
+        if B.ndim not in (1, 2):
+            raise ValueError("B must be (n,) or (n, k)")
         vec = B.ndim == 1
         B2 = np.ascontiguousarray(B.reshape(B.shape[0], -1), dtype=np.float64)
         n, k = B2.shape
+        if A.ndim != 2 or A.shape != (n, n):
+            raise ValueError(f"A must be ({n}, {n}) (got {A.shape})")
+        if out is not None:
+            if (out.dtype != np.float64 or not out.flags.c_contiguous or
+                    out.size != n * k or out.shape[0] != n):
+                raise ValueError("out must be a C-contiguous float64 array shaped like B")
         X = out if out is not None else np.zeros((n, k), dtype=np.float64)
         req = _lib.Request()
         req.n, req.k = n, k
         req.A, req.lda = A.ctypes.data, A.shape[1]
         req.B, req.ldb = B2.ctypes.data, k
-        req.X, req.ldx = X.ctypes.data, X.shape[1] if X.ndim == 2 else 1
+        req.X, req.ldx = X.ctypes.data, k
         req.sweep_dtype = {"f32": 1, "bf16": 2}[sweep_dtype]
         req.rel_tol = rel_tol
         t = ctypes.c_uint64()
@@ -67,7 +75,7 @@ class Server:
         with self._mu:
             A, B2, X, vec = self._keep.get(t, (None, None, None, False))
         d = info.as_dict()
-        return (X[:, 0] if (vec and X is not None) else X), d
+        return (X[:, 0] if (vec and X is not None and X.ndim == 2) else X), d
 
     def poll(self, t):
         info = _lib.Info()
