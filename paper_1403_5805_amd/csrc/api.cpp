@@ -69,14 +69,21 @@ jacobi_status ctx_init(jacobi_ctx* c, int device) {
         return JACOBI_ERR_OUT_OF_MEMORY;
     if (hipEventCreate(&c->ev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipEventCreate(&c->ev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
+    if (hipEventCreate(&c->bev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
+    if (hipEventCreate(&c->bev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
     return JACOBI_OK;
 }
 
 void ctx_release(jacobi_ctx* c) {
     hipSetDevice(c->device);
     for (DevBuf* b : {&c->diag, &c->w0, &c->w1, &c->alo, &c->diag_lo, &c->xa, &c->xb, &c->r64,
-                      &c->rlo, &c->d0, &c->d1, &c->scal, &c->bws, &c->bmeta})
+                      &c->rlo, &c->d0, &c->d1, &c->scal, &c->bws, &c->bmeta, &c->rmeta,
+                      &c->xT})
         b->release();
+    if (c->h_rst) hipHostFree(c->h_rst);
+    c->h_rst = nullptr;
+    if (c->bev_begin) hipEventDestroy(c->bev_begin);
+    if (c->bev_end) hipEventDestroy(c->bev_end);
     if (c->ctl) hipFree(c->ctl);
     if (c->slots) hipFree(c->slots);
     if (c->parts) hipFree(c->parts);

@@ -121,7 +121,7 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
                                hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_off, plan.job_off.data(), sizeof(int32_t) * plan.job_off.size(),
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(c->ev_begin, s));
+    HIP_TRY(hipEventRecord(c->bev_begin, s));
     HIP_TRY(launch_batched_setup(a_dtype, kt, d_sys, d_st, count, nmax, s));
     BatchArgs ba{};
     ba.sys = d_sys;
@@ -137,11 +137,11 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         rate_khz = 100000;
     ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
     if (plan.grid > 0) HIP_TRY(launch_batched(a_dtype, kt, ba, plan.grid, s));
-    HIP_TRY(hipEventRecord(c->ev_end, s));
+    HIP_TRY(hipEventRecord(c->bev_end, s));
     HIP_TRY(hipMemcpyAsync(hst.data(), d_st, sizeof(BState) * count, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->ev_begin, c->ev_end));
+    HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
     for (int i = 0; i < count; ++i) {
         jacobi_info& inf = infos[i];
         const BState& T = hst[i];

@@ -38,6 +38,11 @@ struct jacobi_ctx {
     jac::DevBuf alo, diag_lo, xa, xb, r64, rlo, d0, d1, scal;
     // batched solver: per-system buffers and descriptors
     jac::DevBuf bws, bmeta;
+    hipEvent_t bev_begin = nullptr, bev_end = nullptr;  // batched launch timing
+    // batched FP64 residual: descriptors, transposed iterate, pinned outcomes
+    jac::DevBuf rmeta, xT;
+    jac::RState* h_rst = nullptr;
+    int h_rst_cap = 0;
 };
 
 namespace jac {
@@ -53,6 +58,31 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
                          void* bufs[2], int32_t cap, int32_t sync_every, int profile,
                          hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
                          double* xmax_out, double* kernel_ms, int64_t* launches);
+
+// One system of a batched FP64 residual pass (device pointers; x, d, xnew,
+// r64 and rlo are n x ldx row-major).  xT is workspace of
+// resid_xT_bytes(n, k) bytes.
+struct ResidItem {
+    int64_t n, k, ldx;
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    const double* x;
+    const float* d;
+    double* xnew;
+    double* r64;
+    float* rlo;
+    double* xT;
+    double bnorm, rel;
+};
+
+size_t resid_xT_bytes(int64_t n, int64_t k);
+// Residual pass of `count` systems (k <= 32 each); out[i] receives system i's
+// outcome (host array).  Waits for completion.
+jacobi_status run_resid(jacobi_ctx* c, int32_t count, const ResidItem* items, hipStream_t s,
+                        RState* out);
+
 jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, int64_t lda,
                            const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
                            const jacobi_options& o, hipStream_t s, jacobi_info* info);

@@ -169,6 +169,56 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
 hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int grid,
                           hipStream_t s);
 int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus);
+
+// ---------------------------------------------------------------------------
+// Batched FP64 residual pass (resid.hip): for many systems at once,
+// x_new = x + d, r = B - A x_new, ||r||_2 and the outer stop test of the
+// refinement loop, with the contraction on v_mfma_f64_16x16x4f64 tiles.
+
+// Per-system outcome, written by the last workgroup of the system.
+struct alignas(32) RState {
+    uint32_t stop;       // STOP_RUNNING, STOP_CONVERGED or STOP_DIVERGED
+    uint32_t ticket;     // workgroups of this system done
+    uint64_t rel_bits;   // ||r||_2 / ||b||_2 (||r||_2 when b = 0), double bits
+    uint64_t rmax_bits;  // max |r_ic|, double bits
+    uint64_t pad;
+};
+
+// One system of a batched residual pass (device pointers).  x, d, x_new,
+// r64 and rlo are n x ldx row-major (ldx = padded right-hand-side count).
+struct RSys {
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    const double* x;
+    const float* d;      // correction added to x first, or null
+    double* xnew;        // x + d
+    double* r64;         // residual, FP64
+    float* rlo;          // residual rounded to FP32 (right-hand side of the inner solve)
+    double* xT;          // workspace: (x + d) transposed, kt rows of xld doubles
+    int64_t ldx;
+    int64_t xld;         // multiple of 8, >= n (zero padded)
+    int64_t n;
+    int32_t k;
+    int32_t job0;        // first job (workgroup) of this system
+    int32_t njobs;
+    int32_t aligned;     // rows of A are 16-byte aligned
+    double bnorm;        // ||B||_2 over the k columns
+    double rel;          // stop when ||r||_2 < rel * ||b||_2 (or r == 0)
+};
+
+struct RArgs {
+    const RSys* sys;
+    RState* st;
+    const int32_t* job_sys;  // system of each job
+    double* parts;           // per-job sum of r^2
+};
+
+int resid_tiles(int32_t kt, int64_t n, int num_cus);
+hipError_t launch_resid_prep(int32_t kt, const RSys* sys, RState* st, int32_t count,
+                             int64_t max_xld, hipStream_t s);
+hipError_t launch_resid(int32_t kt, int32_t tiles, const RArgs& a, int32_t jobs, hipStream_t s);
 int batched_waves();
 int batched_unroll(int32_t a_dtype);
 

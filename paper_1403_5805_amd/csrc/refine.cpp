@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "batch.h"
 #include "ctx.h"
 
 namespace jac {
@@ -65,6 +66,12 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     HIP_TRY(c->diag_lo.ensure(4 * n));
     HIP_TRY(c->scal.ensure(64));
     HIP_TRY(c->alo.ensure(elo * (size_t)n * ld_lo));
+    // Several right-hand sides: the residual runs on FP64 MFMA tiles and (from
+    // 8 columns) the inner solve on the FP32 MFMA kernel; one column streams
+    // through the vector kernels.
+    const bool mfma_resid = k >= 2 && k <= 32;
+    const bool mfma_inner = k >= 8 && k <= 32;
+    if (mfma_resid) HIP_TRY(c->xT.ensure(resid_xT_bytes(n, k)));
 
     HIP_TRY(hipEventRecord(c->ev_begin, s));
     // Validation of the FP64 system and x^(0) into xa.
@@ -103,8 +110,33 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     double rel = -1.0, last_delta = -1.0, kms = 0.0;
     int64_t launches = 0;
     jacobi_status result = JACOBI_NOT_CONVERGED;
-    for (;;) {
-        // Residual pass: x <- x + d, r = B - A x, ||r||_2 / ||B||_2.
+    // One residual pass: x <- x + d, r = B - A x, ||r||_2 / ||B||_2.  Leaves
+    // the outcome (STOP_*) in *stop and the relative residual in rel.
+    auto residual_pass = [&](uint32_t* stop) -> jacobi_status {
+        if (mfma_resid) {
+            ResidItem it{};
+            it.n = n;
+            it.k = k;
+            it.ldx = kp;
+            it.A = (const double*)A;
+            it.lda = lda;
+            it.B = (const double*)B;
+            it.ldb = ldb;
+            it.x = (const double*)xcur;
+            it.d = dlt;
+            it.xnew = (double*)xnext;
+            it.r64 = (double*)c->r64.p;
+            it.rlo = (float*)c->rlo.p;
+            it.xT = (double*)c->xT.p;
+            it.bnorm = bnorm;
+            it.rel = o.refine_tol;
+            RState rs{};
+            jacobi_status st = run_resid(c, 1, &it, s, &rs);
+            if (st != JACOBI_OK) return st;
+            *stop = rs.stop;
+            rel = bits_to_double(rs.rel_bits);
+            return JACOBI_OK;
+        }
         HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
         SweepArgs ra{};
         ra.A = A;
@@ -131,24 +163,30 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         ra.r64 = (double*)c->r64.p;
         ra.rlo = (float*)c->rlo.p;
         HIP_TRY(launch_residual(ra, rcfg, s));
-        std::swap(xcur, xnext);
-        outer += 1;
         HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        *stop = c->h_ctl->stop;
         rel = bits_to_double(c->h_ctl->last_delta_bits);
-        if (c->h_ctl->stop == STOP_CONVERGED) {
-            result = JACOBI_OK;
-            break;
+        return JACOBI_OK;
+    };
+    // Inner solve A_lo d = r from d = 0 (relative stop); d is left in *dout.
+    auto inner_solve = [&](const float** dout, uint32_t* stop) -> jacobi_status {
+        if (mfma_inner) {
+            BatchItem it{n, k, c->alo.p, ld_lo, c->rlo.p, kp, nullptr, c->d0.p, kp, o.max_inner};
+            jacobi_options io;
+            jacobi_options_default(&io);
+            io.tol = 0.0;
+            io.max_iter = o.max_inner;
+            jacobi_info ii{};
+            jacobi_status st = run_batched(c, 1, &it, lo, io, TEST_REL, o.inner_rel_tol, s, &ii);
+            if (st != JACOBI_OK) return st;
+            if (ii.status < 0) return (jacobi_status)ii.status;
+            inner_total += ii.iterations;
+            last_delta = ii.final_delta;
+            *stop = ii.status == JACOBI_DIVERGED ? STOP_DIVERGED : STOP_RUNNING;
+            *dout = (const float*)c->d0.p;
+            return JACOBI_OK;
         }
-        if (c->h_ctl->stop == STOP_DIVERGED) {
-            result = JACOBI_DIVERGED;
-            break;
-        }
-        if (outer > o.max_outer) {
-            result = JACOBI_NOT_CONVERGED;
-            break;
-        }
-        // Inner solve A_lo d = r from d = 0.
         HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
         HIP_TRY(launch_zero_rows(4, c->d0.p, kp, n, kp, s));
         HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
@@ -171,18 +209,39 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         ia.norm = JACOBI_NORM_INF;
         ia.aligned = 1;
         void* dbufs[2] = {c->d0.p, c->d1.p};
-        uint32_t stop = 0;
         int32_t K = 0;
         double xmax = 0.0;
         jacobi_status st = run_sweeps(c, lo, ia, icfg, dbufs, o.max_inner, o.sync_every, o.profile,
-                                      s, &stop, &K, &last_delta, &xmax, &kms, &launches);
+                                      s, stop, &K, &last_delta, &xmax, &kms, &launches);
         if (st != JACOBI_OK) return st;
         inner_total += K;
+        *dout = (const float*)dbufs[K & 1];
+        return JACOBI_OK;
+    };
+    for (;;) {
+        uint32_t stop = STOP_RUNNING;
+        jacobi_status st = residual_pass(&stop);
+        if (st != JACOBI_OK) return st;
+        std::swap(xcur, xnext);
+        outer += 1;
+        if (stop == STOP_CONVERGED) {
+            result = JACOBI_OK;
+            break;
+        }
         if (stop == STOP_DIVERGED) {
             result = JACOBI_DIVERGED;
             break;
         }
-        dlt = (const float*)dbufs[K & 1];
+        if (outer > o.max_outer) {
+            result = JACOBI_NOT_CONVERGED;
+            break;
+        }
+        st = inner_solve(&dlt, &stop);
+        if (st != JACOBI_OK) return st;
+        if (stop == STOP_DIVERGED) {
+            result = JACOBI_DIVERGED;
+            break;
+        }
     }
     HIP_TRY(launch_copy_rows(8, xcur, kp, X, ldx, n, (int)k, s));
     HIP_TRY(hipEventRecord(c->ev_end, s));

@@ -8,12 +8,12 @@
 //                   requests already on the device;
 //   compute thread  turns arrived requests into active ones (A_lo = round(A)
 //                   on the device, x = 0) and steps the whole active set: one
-//                   FP64 residual pass per request (x += d fused in), a single
-//                   read-back of every stop flag, retirement of finished
-//                   requests (result copied back, memory freed at once), then
-//                   one persistent batched launch that runs every remaining
-//                   request's inner Jacobi solve A_lo d = r (per system
-//                   relative stop).
+//                   batched FP64 residual launch for every request (x += d
+//                   fused in, stop test per request, one read-back of every
+//                   outcome), retirement of finished requests (result copied
+//                   back, memory freed at once), then one persistent batched
+//                   launch that runs every remaining request's inner Jacobi
+//                   solve A_lo d = r (per system relative stop).
 // Each request's arithmetic depends only on its own data, so its result is
 // the same alone and in any mix.
 #include <hip/hip_runtime.h>
@@ -70,7 +70,7 @@ struct Req {
     double* r64 = nullptr;
     float* rlo = nullptr;
     float* d = nullptr;
-    Ctl* ctl = nullptr;
+    double* xT = nullptr;  // residual workspace (transposed x + d)
     int outer = 0;
     int inner = 0;
     double rel = -1.0;
@@ -86,7 +86,7 @@ size_t footprint(int64_t n, int64_t k, int32_t lo, int64_t* ld_lo_out) {
     const size_t elo = lo == JACOBI_F32 ? 4 : 2;
     size_t b = align256(8 * (size_t)n * n) + align256(elo * (size_t)n * ld_lo) +
                align256(8 * (size_t)n * k) + 3 * align256(8 * (size_t)n * kp) +
-               2 * align256(4 * (size_t)n * kp) + align256(sizeof(Ctl));
+               2 * align256(4 * (size_t)n * kp) + align256(resid_xT_bytes(n, k));
     return b;
 }
 
@@ -115,8 +115,6 @@ struct jacobi_server {
     uint64_t submitted = 0, completed = 0, rejected = 0, failed = 0, steps = 0;
     double t_first = -1.0, t_last = 0.0;
     std::vector<double> lat_e2e, lat_dev;
-    Ctl* h_ctls = nullptr;  // pinned read-back area
-    int h_ctls_cap = 0;
     bool copy_failed = false;
 };
 
@@ -140,6 +138,7 @@ void finish_locked(jacobi_server* s, Req* q, int32_t status) {
 
 void copy_loop(jacobi_server* s) {
     hipSetDevice(s->cfg.device);
+    const bool trace = getenv("JACOBI_SERVE_TRACE") != nullptr;  // per-copy timing to stderr
     for (;;) {
         Req* q = nullptr;
         {
@@ -159,6 +158,7 @@ void copy_loop(jacobi_server* s) {
             s->hbm_peak = std::max(s->hbm_peak, s->hbm_in_use);
         }
         // device state in one stream-ordered allocation
+        const double t_copy0 = now_s();
         void* p = nullptr;
         hipError_t e = hipMallocAsync(&p, q->bytes, s->s_copy);
         const int64_t n = q->r.n, k = q->r.k;
@@ -182,7 +182,7 @@ void copy_loop(jacobi_server* s) {
             b += align256(4 * (size_t)n * q->kp);
             q->d = (float*)b;
             b += align256(4 * (size_t)n * q->kp);
-            q->ctl = (Ctl*)b;
+            q->xT = (double*)b;
             // contiguous rows go as one linear copy (the fast DMA path)
             if (q->r.lda == n)
                 e = hipMemcpyAsync(q->dA, q->r.A, 8 * (size_t)n * n, hipMemcpyHostToDevice,
@@ -199,6 +199,12 @@ void copy_loop(jacobi_server* s) {
                                          hipMemcpyHostToDevice, s->s_copy);
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s->s_copy);
+        }
+        if (trace) {
+            const double dt = now_s() - t_copy0;
+            const double gb = 8.0 * (double)n * (double)(n + k) / 1e9;
+            fprintf(stderr, "[serve] copy n=%lld k=%lld %.2f ms %.2f GB/s\n", (long long)n,
+                    (long long)k, dt * 1e3, gb / dt);
         }
         std::lock_guard<std::mutex> g(s->mu);
         if (e != hipSuccess) {
@@ -260,59 +266,51 @@ void compute_loop(jacobi_server* s) {
         }
         if (act.empty()) continue;
         const double t_step0 = now_s();
-        // 1. FP64 residual pass per request (x += d fused into the staging).
-        if ((int)act.size() > s->h_ctls_cap) {
-            if (s->h_ctls) hipHostFree(s->h_ctls);
-            s->h_ctls_cap = std::max<int>((int)act.size(), 2 * s->h_ctls_cap);
-            hipHostMalloc(&s->h_ctls, sizeof(Ctl) * s->h_ctls_cap, hipHostMallocDefault);
-        }
+        // 1. One batched FP64 residual pass over every active request.
+        std::vector<ResidItem> ritems(act.size());
+        std::vector<RState> rst(act.size());
         for (size_t i = 0; i < act.size(); ++i) {
             Req* q = act[i];
-            launch_init_ctl(q->ctl, s->ctx->slots, 1, s->s_comp);
-            SweepArgs ra{};
-            ra.A = q->dA;
-            ra.lda = q->r.n;
-            ra.B = q->dB;
-            ra.ldb = q->r.k;
-            ra.xin = q->xcur;
-            ra.xout = q->xnext;
-            ra.ldin = q->kp;
-            ra.ldout = q->kp;
-            ra.n = q->r.n;
-            ra.k = (int)q->r.k;
-            ra.kpad = q->kp;
-            ra.sweep = q->outer + 1;
-            ra.seq = 1;
-            ra.ctl = q->ctl;
-            ra.slots = s->ctx->slots;
-            ra.parts = s->ctx->parts;
-            ra.test = TEST_RESID;
-            ra.rel = q->r.rel_tol;
-            ra.bnorm = q->bnorm;
-            ra.aligned = ((q->r.n * 8) % 16 == 0) ? 1 : 0;
-            ra.dlt = q->has_d ? q->d : nullptr;
-            ra.r64 = q->r64;
-            ra.rlo = q->rlo;
-            launch_residual(ra, residual_cfg(q->r.n, (int)q->r.k, s->ctx->num_cus), s->s_comp);
-            hipMemcpyAsync(&s->h_ctls[i], q->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->s_comp);
+            ResidItem& it = ritems[i];
+            it.n = q->r.n;
+            it.k = q->r.k;
+            it.ldx = q->kp;
+            it.A = q->dA;
+            it.lda = q->r.n;
+            it.B = q->dB;
+            it.ldb = q->r.k;
+            it.x = q->xcur;
+            it.d = q->has_d ? q->d : nullptr;
+            it.xnew = q->xnext;
+            it.r64 = q->r64;
+            it.rlo = q->rlo;
+            it.xT = q->xT;
+            it.bnorm = q->bnorm;
+            it.rel = q->r.rel_tol;
         }
-        hipStreamSynchronize(s->s_comp);
+        const jacobi_status rs_st =
+            run_resid(s->ctx, (int32_t)act.size(), ritems.data(), s->s_comp, rst.data());
         const double t_resid = now_s();
         // 2. Decide: retire finished requests, keep the rest.
         std::vector<Req*> keep, done;
         std::vector<int32_t> done_status;
         for (size_t i = 0; i < act.size(); ++i) {
             Req* q = act[i];
+            int32_t st = JACOBI_PENDING;
+            if (rs_st != JACOBI_OK) {
+                // the residual launch failed: fail the whole active set
+                done.push_back(q);
+                done_status.push_back(rs_st);
+                continue;
+            }
             std::swap(q->xcur, q->xnext);
             q->outer += 1;
-            const Ctl& h = s->h_ctls[i];
             double rel;
-            std::memcpy(&rel, &h.last_delta_bits, sizeof(rel));
+            std::memcpy(&rel, &rst[i].rel_bits, sizeof(rel));
             q->rel = rel;
-            int32_t st = JACOBI_PENDING;
-            if (h.stop == STOP_CONVERGED)
+            if (rst[i].stop == STOP_CONVERGED)
                 st = JACOBI_OK;
-            else if (h.stop == STOP_DIVERGED)
+            else if (rst[i].stop == STOP_DIVERGED)
                 st = JACOBI_DIVERGED;
             else if (q->outer > s->cfg.max_outer)
                 st = JACOBI_NOT_CONVERGED;
@@ -617,7 +615,6 @@ jacobi_status jacobi_serve_destroy(jacobi_server* s) {
     hipStreamSynchronize(s->s_comp);
     for (auto& kv : s->all) delete kv.second;
     s->all.clear();
-    if (s->h_ctls) hipHostFree(s->h_ctls);
     hipStreamDestroy(s->s_copy);
     hipStreamDestroy(s->s_comp);
     jacobi_ctx_destroy(s->ctx);

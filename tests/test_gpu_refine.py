@@ -42,6 +42,54 @@ def test_refine_parity(jac, lo, n, k):
     assert np.linalg.norm(R) / np.linalg.norm(B) < 1e-10
 
 
+def _padded(A, pad):
+    """Device copy of A with leading dimension n + pad (odd pad: rows not
+    16-byte aligned)."""
+    import torch
+    n = A.shape[0]
+    big = torch.zeros((n, n + pad), dtype=torch.float64)
+    big[:, :n] = torch.from_numpy(A)
+    return big.cuda()[:, :n]
+
+
+@pytest.mark.parametrize("n,k,pad", [(1, 3, 0), (17, 5, 0), (129, 2, 0), (515, 3, 1),
+                                     (1000, 8, 0), (777, 17, 1), (2047, 32, 0)])
+def test_refine_multi_rhs_parity(jac, n, k, pad):
+    """Several right-hand sides: the FP64 residual runs on MFMA tiles (k >= 2)
+    and the inner solve on the FP32 MFMA kernel (k >= 8); odd leading
+    dimensions take the unaligned load path; n = 1 and ragged n cover the
+    partial tiles and column blocks."""
+    mode = synth.ADDITIVE if n < 32 else synth.MULTIPLICATIVE
+    lo_m, hi_m = (1.0, 2.0) if n < 32 else (0.5, 1.0)
+    A, Xt, B = synth.dominant(n, k, 4200 + n + k, mode, lo_m, hi_m)
+    xr = _xref(A, B)
+    Ad = _padded(A, pad)
+    for lo in ("bf16", "f32"):
+        say("refine multi-rhs", lo, n, k, pad)
+        X, info = jac.solve(Ad, dev(B), mode="refine", sweep_dtype=lo)
+        assert info["status"] == jac.OK, info
+        assert info["rel_residual"] < 1e-12
+        assert rel_err(host(X), xr) <= REL_REFINE, (lo, n, k)
+        R = oracle.residual(A, B, host(X))
+        assert np.linalg.norm(R) / np.linalg.norm(B) < 1e-10
+
+
+@pytest.mark.parametrize("n,k,pad", [(1, 2, 0), (63, 4, 1), (300, 16, 0), (1001, 17, 1),
+                                     (4099, 32, 0), (2000, 1, 0)])
+def test_fp64_residual_pass(jac, n, k, pad):
+    """One residual pass from a random x0 (max_outer = 0): X comes back as x0
+    bitwise and ||B - A x0||_2 / ||B||_2 matches the oracle's residual (no
+    cancellation, so the two agree to rounding)."""
+    A, _, B = synth.dominant(n, k, 4300 + n + k, synth.ADDITIVE, 1.0, 2.0)
+    x0 = np.random.default_rng(n + k).uniform(-1, 1, size=(n, k))
+    say("fp64 residual", n, k, pad)
+    X, info = jac.solve(_padded(A, pad), dev(B), dev(x0), mode="refine", max_outer=0)
+    assert info["status"] == jac.NOT_CONVERGED and info["outer_iterations"] == 1
+    assert np.array_equal(host(X), x0)
+    ref = np.linalg.norm(oracle.residual(A, B, x0)) / np.linalg.norm(B)
+    assert abs(info["rel_residual"] - ref) <= 1e-12 * ref
+
+
 def test_refine_caps_and_x0(jac):
     """max_outer = 0 returns X0 after one residual evaluation; a good X0 is
     accepted at once (one residual pass, no inner sweep)."""
