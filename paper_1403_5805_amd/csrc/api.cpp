@@ -55,6 +55,31 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+hipError_t HostStage::ensure(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    release();
+    const size_t want = std::max<size_t>(b, 64 * 1024);
+    hipError_t e = hipHostMalloc(&h, want, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        h = nullptr;
+        return e;
+    }
+    e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+        hipHostFree(h);
+        h = d = nullptr;
+        return e;
+    }
+    bytes = want;
+    return hipSuccess;
+}
+
+void HostStage::release() {
+    if (h) hipHostFree(h);
+    h = d = nullptr;
+    bytes = 0;
+}
+
 jacobi_status ctx_init(jacobi_ctx* c, int device) {
     c->device = device;
     hipDeviceProp_t prop;
@@ -80,8 +105,7 @@ void ctx_release(jacobi_ctx* c) {
                       &c->rlo, &c->d0, &c->d1, &c->scal, &c->bws, &c->bmeta, &c->rmeta,
                       &c->xT})
         b->release();
-    if (c->h_rst) hipHostFree(c->h_rst);
-    c->h_rst = nullptr;
+    c->stage.release();
     if (c->bev_begin) hipEventDestroy(c->bev_begin);
     if (c->bev_end) hipEventDestroy(c->bev_end);
     if (c->ctl) hipFree(c->ctl);

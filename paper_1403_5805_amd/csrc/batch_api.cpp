@@ -49,8 +49,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     }
     std::vector<int64_t> ns(count);
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
-    Plan plan = make_plan(ns, capacity, batched_waves(), batched_unroll(a_dtype),
-                          a_dtype == JACOBI_F32 ? 16 : 32);
+    Plan plan = make_plan(ns, capacity, batched_tiles_per_pass(a_dtype, kt), batched_unroll(a_dtype),
+                          batched_block_cols(a_dtype));
     if (plan.grid > capacity) {
         // a cooperative launch needs every workgroup resident at once
         set_error("batched plan of %d workgroups exceeds the resident grid %d", plan.grid,
@@ -114,13 +114,18 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         T.bad_diag = INT64_MAX;
         T.bad_rhs = INT64_MAX;
     }
-    HIP_TRY(hipMemcpyAsync(d_sys, hs.data(), sizeof(BSys) * count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_st, hst.data(), sizeof(BState) * count, hipMemcpyHostToDevice, s));
+    // Descriptors, initial states, job table and offsets go up through the
+    // pinned stage in one copy kernel; the states come back the same way.
+    const size_t up_b = sys_b + st_b + job_b + off_b;
+    HIP_TRY(c->stage.ensure(up_b + st_b));
+    char* h = (char*)c->stage.h;
+    std::memcpy(h, hs.data(), sizeof(BSys) * count);
+    std::memcpy(h + sys_b, hst.data(), sizeof(BState) * count);
     if (!plan.jobs.empty())
-        HIP_TRY(hipMemcpyAsync(d_jobs, plan.jobs.data(), sizeof(BJob) * plan.jobs.size(),
-                               hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_off, plan.job_off.data(), sizeof(int32_t) * plan.job_off.size(),
-                           hipMemcpyHostToDevice, s));
+        std::memcpy(h + sys_b + st_b, plan.jobs.data(), sizeof(BJob) * plan.jobs.size());
+    std::memcpy(h + sys_b + st_b + job_b, plan.job_off.data(),
+                sizeof(int32_t) * plan.job_off.size());
+    HIP_TRY(launch_copy16(c->stage.d, meta, up_b, s));
     HIP_TRY(hipEventRecord(c->bev_begin, s));
     HIP_TRY(launch_batched_setup(a_dtype, kt, d_sys, d_st, count, nmax, s));
     BatchArgs ba{};
@@ -138,8 +143,9 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
     if (plan.grid > 0) HIP_TRY(launch_batched(a_dtype, kt, ba, plan.grid, s));
     HIP_TRY(hipEventRecord(c->bev_end, s));
-    HIP_TRY(hipMemcpyAsync(hst.data(), d_st, sizeof(BState) * count, hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_copy16(d_st, (char*)c->stage.d + up_b, st_b, s));
     HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(hst.data(), h + up_b, sizeof(BState) * count);
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
     for (int i = 0; i < count; ++i) {

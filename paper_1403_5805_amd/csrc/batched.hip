@@ -5,16 +5,20 @@
 // S = (A - D) X followed by x_new = (b - s) / a_ii (the component equation of
 // sec. 2 of the paper applied to every column), is a dense n x n by n x k
 // contraction, done on v_mfma_f32_16x16x4_f32:
-//   * a wave owns a 16-row tile; lane l loads row (l % 16) and 16 bytes of
-//     consecutive columns (4 FP32 or 8 BF16 values) at column group l / 16,
-//     so one 16-byte load per lane feeds 4 (FP32) or 8 (BF16) MFMA k-steps;
+//   * a workgroup sweeps its rows in passes of TPW 16-row tiles; all W waves
+//     work on the same tiles and split the columns (wave w takes every W-th
+//     block), and their partial tiles are added in wave order through LDS, so
+//     even a system of a few hundred rows keeps every wave streaming;
+//   * lane l loads row (l % 16) of a tile, 16 bytes of consecutive columns
+//     (4 FP32 or 8 BF16 values) at column group l / 16, so one load feeds 4
+//     (FP32) or 8 (BF16) MFMA k-steps;
 //   * the iterate is kept transposed in global memory (column c of X is a
-//     contiguous row of xld floats), so the matching B operand of 4 k-steps
-//     is one 16-byte load that hits L1/L2 (X is small and every tile of the
-//     system reads it); no LDS staging and no barrier inside a sweep: the
-//     waves of a workgroup stream their 16-row tiles independently;
+//     contiguous row of xld floats, zero padded), so the matching B operand
+//     of 4 k-steps is one 16-byte load that hits the L2 (X is small and every
+//     tile of the system reads it); nothing is staged and no barrier runs
+//     inside a pass;
 //   * the diagonal term is masked in the A operand (sum over j != i);
-//   * the accumulator tile is the epilogue's input: division by a_ii, the
+//   * the reduced tile is the epilogue's input: division by a_ii, the
 //     distance max|x_new - x_old| (or its Euclidean form) and the stop test.
 // Systems are planned on the host: a large system is split over several
 // workgroups that meet at a per-system barrier (atomic counter) after every
@@ -36,6 +40,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 __device__ __forceinline__ float bf_to_f(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Pointers into global memory.  The system descriptors live in device memory,
+// so the compiler cannot infer the address space of the pointers they hold and
+// would emit flat loads, which force a full wait on every outstanding load and
+// defeat the load pipeline below.
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(const T* p) {
+    return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ T __attribute__((address_space(1)))* gout(T* p) {
+    return (T __attribute__((address_space(1)))*)p;
+}
 
 template <typename TA>
 __device__ __forceinline__ void unpack(const u32x4& v, float* a);
@@ -90,12 +109,6 @@ __device__ __forceinline__ uint64_t wmax(uint64_t v) {
 
 }  // namespace
 
-// x rows staged in LDS per chunk: 64 KiB of FP32 for the chunk.
-template <int KT>
-constexpr int batched_chunk_cols() {
-    return KT <= 16 ? 1024 : 512;
-}
-
 // ---------------------------------------------------------------------------
 // Setup: per system, gather alpha_ii, validate (zero / non-finite diagonal,
 // non-finite B or X0), write X0 (or zeros) transposed into buf0 and clear
@@ -140,19 +153,16 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
-//   W   waves per workgroup
-//   TPW 16-row tiles per wave in one pass (they share every B operand read)
-//   U   A blocks per pipeline stage (two stages in flight)
+//   W   waves per workgroup (they split the columns of every tile)
+//   TPW 16-row tiles per pass (they share every B operand load)
+//   U   column blocks per pipeline stage (two stages in flight)
 template <typename TA, int KT, int W, int TPW, int U>
 __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
     constexpr int VEC = 16 / (int)sizeof(TA);  // A values per 16-byte lane load
     constexpr int BW = 4 * VEC;                // columns of one A block (16 or 32)
     constexpr int NT = KT / 16;                // 16-column output tiles
     constexpr int NS = VEC / 4;                // 4-step MFMA groups per block
-    constexpr int CH = batched_chunk_cols<KT>();  // x rows staged per chunk
-    constexpr int CHP = CH + 4;                // padded LDS row (bank spread)
-    static_assert(CH % (BW * U) == 0, "a pipeline stage never straddles chunks");
-    extern __shared__ __attribute__((aligned(16))) float xsT[];  // [KT][CHP]
+    __shared__ float red[W * TPW * NT * 256];
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ uint32_t s_flag;
@@ -176,8 +186,10 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
         const int k = S.k;
         const bool split = S.nwg > 1;
         const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
-        const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks fully inside n
-        const int64_t nfull = (nbf / U) * U;           // blocks handled by the pipeline
+        const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks loadable with 16-byte loads
+        // this wave's vector-loadable blocks: b = wave + W * t, t < ntw
+        const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
+        const int64_t nfull = (ntw / U) * U;
         const float* xfinal = S.buf0;
         int32_t final_k = 0;
         uint32_t final_stop = STOP_RUNNING;
@@ -189,60 +201,45 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
             float* xout = (sweep & 1) ? S.buf1 : S.buf0;
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * W * TPW) {
+            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * TPW) {
                 int64_t rt[TPW];
-                const TA* arow[TPW];
+                gptr<TA> arow[TPW];
 #pragma unroll
                 for (int q = 0; q < TPW; ++q) {
-                    rt[q] = pr + 16 * (wave + W * q);
+                    rt[q] = pr + 16 * q;
                     int64_t ri = rt[q] + li;
-                    if (rt[q] >= job.r1) ri = job.r0;  // idle tile: load a valid row, discard
-                    if (ri >= n) ri = n - 1;
-                    arow[q] = A + ri * S.lda + VEC * grp;
+                    // rows past the job (a short last pass): re-read the
+                    // job's last row, which the cache serves, and discard
+                    if (ri >= job.r1) ri = job.r1 - 1;
+                    arow[q] = gbl(A + ri * S.lda + VEC * grp);
                 }
+                gptr<float> xrow[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
                 f32x4 acc[TPW][NT];
 #pragma unroll
                 for (int q = 0; q < TPW; ++q)
 #pragma unroll
                     for (int t = 0; t < NT; ++t) acc[q][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-                // x chunk staging: X is stored transposed, so a chunk is KT
-                // contiguous row pieces (zero padded past n in global memory).
-                int64_t cur_chunk = -1;
-                auto ensure_chunk = [&](int64_t b) {
-                    const int64_t ch = (b * BW) / CH;
-                    if (ch == cur_chunk) return;
-                    const int64_t c0 = ch * CH;
-                    const int64_t cl = (n - c0) < CH ? (n - c0) : CH;
-                    const int64_t clp = (cl + BW - 1) / BW * BW;
-                    const int nq = (int)(clp / 4);
-                    __syncthreads();
-                    for (int e = tid; e < KT * nq; e += W * 64) {
-                        const int c = e / nq, j4 = e - c * nq;
-                        *reinterpret_cast<f32x4*>(xsT + c * CHP + 4 * j4) =
-                            *reinterpret_cast<const f32x4*>(xin + (int64_t)c * xld + c0 + 4 * j4);
-                    }
-                    __syncthreads();
-                    cur_chunk = ch;
-                };
-                // MFMAs of one A block (TPW tiles share the B operand).
-                auto mfma_block = [&](float (&a)[TPW][VEC], int64_t b) {
-                    const int jrel = (int)(b * BW - cur_chunk * CH);
-                    f32x4 bx[NT][NS];
+                auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
 #pragma unroll
                         for (int sg = 0; sg < NS; ++sg)
-                            bx[t][sg] = *reinterpret_cast<const f32x4*>(
-                                xsT + (t * 16 + li) * CHP + jrel + VEC * grp + 4 * sg);
-                    const int64_t colbase = b * BW + VEC * grp;
+                            bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
+                };
+                // MFMAs of one A block (the TPW tiles share the B operand).
+                auto mfma_block = [&](float (&a)[TPW][VEC], const f32x4 (&bx)[NT][NS], int64_t b) {
 #pragma unroll
                     for (int q = 0; q < TPW; ++q) {
-                        if (b * BW < rt[q] + 16 && rt[q] < b * BW + BW) {
+                        // Mask the diagonal without a branch: the lane's row
+                        // rt + li sits at element dpos of its load (rows and
+                        // columns are below 2^31).
+                        const int dpos = (int)rt[q] - (int)(b * BW) + li - VEC * grp;
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e)
-                                if (colbase + e == rt[q] + li) a[q][e] = 0.0f;
-                        }
+                        for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
 #pragma unroll
                         for (int sg = 0; sg < NS; ++sg)
 #pragma unroll
@@ -253,48 +250,62 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                                         a[q][4 * sg + r], bx[t][sg][r], acc[q][t], 0, 0, 0);
                     }
                 };
-                // Full blocks: two pipeline stages of U blocks; the A loads of
-                // the next stage are in flight during the MFMAs (and the chunk
-                // staging) of the current one.
+                // Vector-loadable blocks: two pipeline stages of U blocks; the
+                // loads of one stage are in flight during the MFMAs of the other.
                 if (nfull > 0) {
                     u32x4 v0[U][TPW], v1[U][TPW];
-                    auto issue = [&](u32x4 (&v)[U][TPW], int64_t bb) {
+                    f32x4 b0[U][NT][NS], b1[U][NT][NS];
+                    auto issue = [&](u32x4 (&v)[U][TPW], f32x4 (&bx)[U][NT][NS], int64_t t0) {
 #pragma unroll
-                        for (int u = 0; u < U; ++u)
+                        for (int u = 0; u < U; ++u) {
+                            const int64_t b = wave + W * (t0 + u);
 #pragma unroll
                             for (int q = 0; q < TPW; ++q)
-                                v[u][q] = __builtin_nontemporal_load(
-                                    reinterpret_cast<const u32x4*>(arow[q] + (bb + u) * BW));
+                                v[u][q] = __builtin_nontemporal_load((gptr<u32x4>)(arow[q] + b * BW));
+                            load_b(bx[u], b);
+                        }
                     };
-                    auto consume = [&](u32x4 (&v)[U][TPW], int64_t bb) {
-                        ensure_chunk(bb);
+                    auto consume = [&](u32x4 (&v)[U][TPW], f32x4 (&bx)[U][NT][NS], int64_t t0) {
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             float a[TPW][VEC];
 #pragma unroll
                             for (int q = 0; q < TPW; ++q) unpack<TA>(v[u][q], a[q]);
-                            mfma_block(a, bb + u);
+                            mfma_block(a, bx[u], wave + W * (t0 + u));
                         }
                     };
-                    issue(v0, 0);
-                    int64_t b0 = 0;
-                    for (; b0 + 2 * U <= nfull; b0 += 2 * U) {
-                        issue(v1, b0 + U);
-                        consume(v0, b0);
-                        if (b0 + 2 * U < nfull) issue(v0, b0 + 2 * U);
-                        consume(v1, b0 + U);
+                    // The scheduling barriers keep the compiler from sinking
+                    // the loads below the MFMAs that should hide them.
+                    issue(v0, b0, 0);
+                    int64_t t = 0;
+                    for (; t + 3 * U <= nfull; t += 2 * U) {
+                        issue(v1, b1, t + U);
+                        __builtin_amdgcn_sched_barrier(0);
+                        consume(v0, b0, t);
+                        __builtin_amdgcn_sched_barrier(0);
+                        issue(v0, b0, t + 2 * U);
+                        __builtin_amdgcn_sched_barrier(0);
+                        consume(v1, b1, t + U);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    if (b0 < nfull) consume(v0, b0);
+                    if (t + 2 * U <= nfull) {
+                        issue(v1, b1, t + U);
+                        __builtin_amdgcn_sched_barrier(0);
+                        consume(v0, b0, t);
+                        __builtin_amdgcn_sched_barrier(0);
+                        consume(v1, b1, t + U);
+                    } else {
+                        consume(v0, b0, t);
+                    }
                 }
-                // Remaining blocks (ragged tail, or every block of unaligned rows).
-                for (int64_t b = nfull; b < nb; ++b) {
-                    ensure_chunk(b);
+                // Remaining blocks of this wave (ragged tail, or every block of
+                // rows that are not 16-byte aligned).
+                for (int64_t b = wave + W * nfull; b < nb; b += W) {
                     float a[TPW][VEC];
 #pragma unroll
                     for (int q = 0; q < TPW; ++q) {
                         if (b < nbf) {
-                            const u32x4 v = __builtin_nontemporal_load(
-                                reinterpret_cast<const u32x4*>(arow[q] + b * BW));
+                            const u32x4 v = __builtin_nontemporal_load((gptr<u32x4>)(arow[q] + b * BW));
                             unpack<TA>(v, a[q]);
                         } else {
 #pragma unroll
@@ -304,43 +315,44 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                             }
                         }
                     }
-                    mfma_block(a, b);
+                    f32x4 bx[NT][NS];
+                    load_b(bx, b);  // zero padded past n
+                    mfma_block(a, bx, b);
                 }
-                // epilogue: lane holds rows rt + 4*grp + v, column t*16 + li
+                // Add the W partial tiles in wave order.  Tile element (i, j)
+                // sits in lane 16 * (i / 4) + j, register i % 4.
 #pragma unroll
-                for (int q = 0; q < TPW; ++q) {
-                    if (rt[q] >= job.r1) continue;
-                    const int64_t i0 = rt[q] + 4 * grp;
+                for (int q = 0; q < TPW; ++q)
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        const int c = t * 16 + li;
-                        const f32x4 xo4 =
-                            *reinterpret_cast<const f32x4*>(xin + (int64_t)c * xld + i0);
-                        f32x4 xn4 = xo4;
+                    for (int t = 0; t < NT; ++t)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int64_t i = i0 + v;
-                            if (i < job.r1 && c < k) {
-                                const float xn = (S.B[i * S.ldb + c] - acc[q][t][v]) / S.diag[i];
-                                xn4[v] = xn;
-                                const double dd = fabs((double)xn - (double)xo4[v]);
-                                const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
-                                dmax = db > dmax ? db : dmax;
-                                xmax = mb > xmax ? mb : xmax;
-                                sq += dd * dd;
-                            }
-                        }
-                        // rows past r1 keep their value (zero padding or another
-                        // workgroup's rows)
-                        if (i0 + 3 < job.r1) {
-                            *reinterpret_cast<f32x4*>(xout + (int64_t)c * xld + i0) = xn4;
-                        } else {
+                        for (int v = 0; v < 4; ++v)
+                            red[(((wave * TPW + q) * NT + t) * 4 + v) * 64 + lane] = acc[q][t][v];
+                __syncthreads();
+                // Epilogue: thread e takes column cc of tile (q, t), row ri, so
+                // consecutive threads write consecutive rows of the transposed
+                // iterate.
+                for (int e = tid; e < TPW * NT * 256; e += W * 64) {
+                    const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+                    const int q = qt / NT, t = qt - q * NT;
+                    const int l = 16 * (ri >> 2) + cc, v = ri & 3;
+                    float s = 0.0f;
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (i0 + v < job.r1) xout[(int64_t)c * xld + i0 + v] = xn4[v];
-                        }
+                    for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
+                    const int64_t i = pr + 16 * q + ri;
+                    const int c = t * 16 + cc;
+                    if (i < job.r1 && c < k) {
+                        const float xo = *gbl(xin + (int64_t)c * xld + i);
+                        const float xn = (*gbl(S.B + i * S.ldb + c) - s) / *gbl(S.diag + i);
+                        *gout(xout + (int64_t)c * xld + i) = xn;
+                        const double dd = fabs((double)xn - (double)xo);
+                        const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                        dmax = db > dmax ? db : dmax;
+                        xmax = mb > xmax ? mb : xmax;
+                        sq += dd * dd;
                     }
                 }
+                __syncthreads();  // red is reused by the next pass
             }
             // ---- workgroup reduction of the distance statistics
             dmax = wmax(dmax);
@@ -351,8 +363,7 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                 red_m[wave] = xmax;
                 red_s[wave] = sq;
             }
-            if (split) __threadfence();  // publish x_new before the system barrier
-            __syncthreads();
+            __syncthreads();  // every wave's x_new stores precede tid 0's release below
             if (tid == 0) {
                 uint64_t D = 0, M = 0;
                 double Q = 0.0;
@@ -380,12 +391,14 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                         __hip_atomic_store(&st->xmax[nxt], (uint64_t)0, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    __threadfence();
+                    // One release (the atomic) and one acquire (the fence after
+                    // the wait) per sweep: each writes back or invalidates the
+                    // L2, so the wait itself polls with relaxed loads.
                     __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     const uint32_t target = (uint32_t)S.nwg * (uint32_t)sweep;
                     const uint64_t t0 = wall_clock64();
-                    while (__hip_atomic_load(&st->counter, __ATOMIC_ACQUIRE,
+                    while (__hip_atomic_load(&st->counter, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT) < target) {
                         __builtin_amdgcn_s_sleep(2);
                         if ((int64_t)(wall_clock64() - t0) > p.spin_limit) {
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                             break;
                         }
                     }
-                    __threadfence();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     D = __hip_atomic_load(&st->dmax[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     M = __hip_atomic_load(&st->xmax[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (S.norm == 1) {
@@ -415,8 +428,7 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                 s_flag = flag;
                 s_delta = delta;
             }
-            __syncthreads();
-            if (split) __threadfence();  // acquire the other workgroups' x_new
+            __syncthreads();  // tid 0's acquire precedes every wave's next loads
             const uint32_t flag = s_flag;
             if (flag == 99) {
                 failed = true;
@@ -432,27 +444,13 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
         }
         if (failed) continue;
         // Copy this workgroup's rows of the final iterate to the caller's X.
-        // In the last sweep each element was written by the thread that copies
-        // it here (same tile walk), so no further synchronisation is needed.
-        if (final_k > 0) {
-            for (int64_t rt = job.r0 + 16 * wave; rt < job.r1; rt += 16 * W) {
-                // same (row, column) -> thread map as the epilogue: tile
-                // pr + 16*(wave + W*q) is walked by this wave for every pass
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t i = rt + 4 * grp + v;
-                        const int c = t * 16 + li;
-                        if (i < job.r1 && c < k) S.X[i * S.ldx + c] = xfinal[(int64_t)c * xld + i];
-                    }
-            }
-        } else {
-            for (int64_t e = tid; e < (job.r1 - job.r0) * k; e += W * 64) {
-                const int64_t i = job.r0 + e / k;
-                const int c = (int)(e % k);
-                S.X[i * S.ldx + c] = S.buf0[(int64_t)c * xld + i];
-            }
+        // Every thread of the workgroup wrote its share of them before the
+        // barriers that closed the last sweep.
+        const float* xsrc = final_k > 0 ? xfinal : S.buf0;
+        for (int64_t e = tid; e < (job.r1 - job.r0) * k; e += W * 64) {
+            const int64_t i = job.r0 + e / k;
+            const int c = (int)(e % k);
+            S.X[i * S.ldx + c] = xsrc[(int64_t)c * xld + i];
         }
         if (tid == 0 && job.rank == 0) {
             __hip_atomic_store(&st->status, final_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -466,20 +464,26 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
 
 // ---------------------------------------------------------------------------
 constexpr int kBW = 4;   // waves per workgroup
-constexpr int kTPW = 2;  // 16-row tiles per wave per pass
 constexpr int kBU = 2;   // A blocks per pipeline stage
 
-int batched_waves() { return kBW * kTPW; }  // 16-row tiles per workgroup pass
-int batched_unroll(int32_t) { return 2 * kBU; }
-
-static size_t batched_lds(int32_t kt) {
-    return (size_t)kt * ((kt <= 16 ? batched_chunk_cols<16>() : batched_chunk_cols<32>()) + 4) *
-           sizeof(float);
+// 16-row tiles per pass: more tiles share each B operand load; 32 output
+// columns, or BF16 blocks (8 values per load), leave registers for fewer.
+template <typename TA>
+constexpr int tiles_per_pass(int kt) {
+    return (kt <= 16 && sizeof(TA) == 4) ? 4 : 2;
 }
+
+// Shape parameters seen by the host planner: tiles per pass and the columns
+// one wave covers per pipeline round trip.
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt) {
+    return a_dtype == 1 ? tiles_per_pass<float>(kt) : tiles_per_pass<bf16_t>(kt);
+}
+int batched_unroll(int32_t) { return 2 * kBU; }
+int batched_block_cols(int32_t a_dtype) { return kBW * (a_dtype == 1 ? 16 : 32); }
 
 template <typename TA, int KT>
 static const void* batched_fn() {
-    return (const void*)k_batched<TA, KT, kBW, kTPW, kBU>;
+    return (const void*)k_batched<TA, KT, kBW, tiles_per_pass<TA>(KT), kBU>;
 }
 
 static const void* pick(int32_t a_dtype, int32_t kt) {
@@ -491,10 +495,8 @@ static const void* pick(int32_t a_dtype, int32_t kt) {
 int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus) {
     const void* fn = pick(a_dtype, kt);
     if (!fn) return 0;
-    const size_t lds = batched_lds(kt);
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu * num_cus;
@@ -517,12 +519,9 @@ hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int g
                           hipStream_t s) {
     const void* fn = pick(a_dtype, kt);
     if (!fn) return hipErrorInvalidValue;
-    const size_t lds = batched_lds(kt);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
     BatchArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBW * 64), args, (unsigned)lds, s);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBW * 64), args, 0u, s);
 }
 
 }  // namespace jac

@@ -20,6 +20,18 @@ struct DevBuf {
     void release();
 };
 
+// Grow-only pinned, device-mapped host buffer for the small per-call
+// descriptor uploads and outcome read-backs.  They are moved by a copy kernel
+// on the caller's stream rather than by the DMA engines, so they never queue
+// behind large host transfers running on other streams.
+struct HostStage {
+    void* h = nullptr;  // host address
+    void* d = nullptr;  // device address of the same memory
+    size_t bytes = 0;
+    hipError_t ensure(size_t b);
+    void release();
+};
+
 }  // namespace jac
 
 struct jacobi_ctx {
@@ -41,8 +53,8 @@ struct jacobi_ctx {
     hipEvent_t bev_begin = nullptr, bev_end = nullptr;  // batched launch timing
     // batched FP64 residual: descriptors, transposed iterate, pinned outcomes
     jac::DevBuf rmeta, xT;
-    jac::RState* h_rst = nullptr;
-    int h_rst_cap = 0;
+    // staging for descriptor uploads and outcome read-backs
+    jac::HostStage stage;
 };
 
 namespace jac {

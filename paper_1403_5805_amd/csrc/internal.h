@@ -215,12 +215,16 @@ struct RArgs {
     double* parts;           // per-job sum of r^2
 };
 
+// Copy `bytes` (a multiple of 16, 16-byte aligned ends) with a kernel.
+hipError_t launch_copy16(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 int resid_tiles(int32_t kt, int64_t n, int num_cus);
 hipError_t launch_resid_prep(int32_t kt, const RSys* sys, RState* st, int32_t count,
                              int64_t max_xld, hipStream_t s);
 hipError_t launch_resid(int32_t kt, int32_t tiles, const RArgs& a, int32_t jobs, hipStream_t s);
-int batched_waves();
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt);
 int batched_unroll(int32_t a_dtype);
+int batched_block_cols(int32_t a_dtype);
 
 // Default launch configuration for a sweep of this shape.
 LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus);

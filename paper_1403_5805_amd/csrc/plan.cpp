@@ -10,13 +10,13 @@
 namespace jac {
 
 // Modelled time of one sweep of rows [0, rows) of an n-column system on one
-// workgroup: each wave walks ceil(tiles / W) 16-row tiles, each tile takes
-// ceil(blocks / U) load round trips plus its epilogue.  Units are arbitrary;
-// only ratios matter.
-static double job_cost(int64_t n, int64_t rows, int waves, int unroll, int bw) {
-    const double tiles_per_wave = std::ceil(std::ceil((double)rows / 16.0) / waves);
+// workgroup: ceil(tiles / tpp) passes, each taking ceil(blocks / U) load
+// round trips (a round trip covers bw columns of every tile of the pass) plus
+// its epilogue.  Units are arbitrary; only ratios matter.
+static double job_cost(int64_t n, int64_t rows, int tpp, int unroll, int bw) {
+    const double passes = std::ceil(std::ceil((double)rows / 16.0) / tpp);
     const double blocks = std::ceil((double)n / bw);
-    return tiles_per_wave * (1.0 + std::ceil(blocks / unroll)) + 1.0;
+    return passes * (1.0 + std::ceil(blocks / unroll)) + 1.0;
 }
 
 // Split big systems over several workgroups and pack small systems whole
@@ -24,7 +24,7 @@ static double job_cost(int64_t n, int64_t rows, int waves, int unroll, int bw) {
 // modelled sweep time above.  A workgroup that shares a system with others
 // owns nothing else, so barrier waits only involve workgroups that are certain
 // to arrive.
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw) {
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw) {
     Plan p;
     const int count = (int)n.size();
     p.nwg.assign(count, 1);
@@ -35,7 +35,7 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unrol
     std::vector<double> cost(count);
     double total = 0.0;
     for (int i = 0; i < count; ++i) {
-        cost[i] = job_cost(n[i], n[i], waves, unroll, bw);
+        cost[i] = job_cost(n[i], n[i], tpp, unroll, bw);
         total += cost[i];
     }
     const double target = total / std::max(1, capacity);
@@ -44,7 +44,8 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unrol
     for (int i = 0; i < count; ++i) {
         const int64_t tiles = (n[i] + 15) / 16;
         int want = (int)std::lround(cost[i] / target);
-        want = (int)std::min<int64_t>(want, tiles);
+        // no share smaller than one full pass of tiles
+        want = (int)std::min<int64_t>(want, (tiles + tpp - 1) / tpp);
         if (want >= 2) {
             p.nwg[i] = want;
             big.push_back(i);

@@ -26,11 +26,11 @@ struct Plan {
 };
 
 // Plan `n.size()` systems (sizes n[i]) onto at most `capacity` co-resident
-// workgroups of `waves` waves that issue `unroll` loads of `bw` columns per
-// round trip.  Guarantees: grid <= capacity; the jobs of system i cover its
+// workgroups that sweep `tpp` 16-row tiles per pass and cover `bw` columns of
+// them per load, `unroll` loads per round trip.  Guarantees: grid <= capacity; the jobs of system i cover its
 // rows [0, n[i]) exactly once, split at multiples of 16 rows; a system split
 // over nwg[i] >= 2 workgroups has one job of each rank 0..nwg[i]-1, and a
 // workgroup holding such a job holds nothing else.
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int waves, int unroll, int bw);
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw);
 
 }  // namespace jac

@@ -29,6 +29,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace jac {
@@ -133,77 +135,96 @@ __global__ __launch_bounds__(W * 64) void k_resid(RArgs p) {
     // this wave's full blocks: b = wave + W * t, t < ntw
     const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
     const int64_t nfull = (ntw / U) * U;
-    const bool vec = S.aligned != 0;
-
-    auto load_a = [&](f64x2 (&a)[TPW], int64_t b) {
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            const double* src = arow[q] + b * BW;
-            if (vec) {
-                a[q] = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
-            } else {
-                a[q].x = __builtin_nontemporal_load(src);
-                a[q].y = __builtin_nontemporal_load(src + 1);
-            }
-        }
-    };
-    auto load_b = [&](f64x2 (&x)[NT], int64_t b) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const f64x2*>(xrow[t] + b * BW);
-    };
-    auto mma = [&](const f64x2 (&a)[TPW], const f64x2 (&x)[NT]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][s], x[t][s], acc[q][t],
-                                                                     0, 0, 0);
-    };
-
-    // Full blocks: two pipeline stages of U blocks, the loads of one stage in
-    // flight while the MFMAs of the other run.
-    if (nfull > 0) {
-        f64x2 a0[U][TPW], x0[U][NT], a1[U][TPW], x1[U][NT];
-        auto issue = [&](f64x2 (&a)[U][TPW], f64x2 (&x)[U][NT], int64_t t0) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t b = wave + W * (t0 + u);
-                load_a(a[u], b);
-                load_b(x[u], b);
-            }
-        };
-        auto consume = [&](f64x2 (&a)[U][TPW], f64x2 (&x)[U][NT]) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) mma(a[u], x[u]);
-        };
-        issue(a0, x0, 0);
-        int64_t t = 0;
-        for (; t + 2 * U <= nfull; t += 2 * U) {
-            issue(a1, x1, t + U);
-            consume(a0, x0);
-            if (t + 2 * U < nfull) issue(a0, x0, t + 2 * U);
-            consume(a1, x1);
-        }
-        if (t < nfull) consume(a0, x0);
-    }
-    // Remaining full blocks of this wave and the ragged last block.
-    for (int64_t b = wave + W * nfull; b < nb; b += W) {
-        f64x2 a[TPW], x[NT];
-        if (b < nbf) {
-            load_a(a, b);
-        } else {
+    // The main loop, compiled once for 16-byte row loads (rows 16-byte
+    // aligned) and once for pairs of 8-byte loads.
+    auto run = [&](auto vec_tag) {
+        constexpr bool VEC16 = decltype(vec_tag)::value;
+        auto load_a = [&](f64x2 (&a)[TPW], int64_t b) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
-                const int64_t col = b * BW + 2 * grp;
-                a[q].x = col < n ? arow[q][b * BW] : 0.0;
-                a[q].y = col + 1 < n ? arow[q][b * BW + 1] : 0.0;
+                const double* src = arow[q] + b * BW;
+                if constexpr (VEC16) {
+                    a[q] = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
+                } else {
+                    a[q].x = __builtin_nontemporal_load(src);
+                    a[q].y = __builtin_nontemporal_load(src + 1);
+                }
+            }
+        };
+        auto load_b = [&](f64x2 (&x)[NT], int64_t b) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const f64x2*>(xrow[t] + b * BW);
+        };
+        auto mma = [&](const f64x2 (&a)[TPW], const f64x2 (&x)[NT]) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][s], x[t][s],
+                                                                         acc[q][t], 0, 0, 0);
+        };
+        // Full blocks: two pipeline stages of U blocks, the loads of one stage
+        // in flight while the MFMAs of the other run; the scheduling barriers
+        // keep the compiler from sinking the loads below those MFMAs.
+        if (nfull > 0) {
+            f64x2 a0[U][TPW], x0[U][NT], a1[U][TPW], x1[U][NT];
+            auto issue = [&](f64x2 (&a)[U][TPW], f64x2 (&x)[U][NT], int64_t t0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t b = wave + W * (t0 + u);
+                    load_a(a[u], b);
+                    load_b(x[u], b);
+                }
+            };
+            auto consume = [&](f64x2 (&a)[U][TPW], f64x2 (&x)[U][NT]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) mma(a[u], x[u]);
+            };
+            issue(a0, x0, 0);
+            int64_t t = 0;
+            for (; t + 3 * U <= nfull; t += 2 * U) {
+                issue(a1, x1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(a0, x0);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(a0, x0, t + 2 * U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(a1, x1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (t + 2 * U <= nfull) {
+                issue(a1, x1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(a0, x0);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(a1, x1);
+            } else {
+                consume(a0, x0);
             }
         }
-        load_b(x, b);  // zero padded past n
-        mma(a, x);
-    }
+        // Remaining full blocks of this wave and the ragged last block.
+        for (int64_t b = wave + W * nfull; b < nb; b += W) {
+            f64x2 a[TPW], x[NT];
+            if (b < nbf) {
+                load_a(a, b);
+            } else {
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    const int64_t col = b * BW + 2 * grp;
+                    a[q].x = col < n ? arow[q][b * BW] : 0.0;
+                    a[q].y = col + 1 < n ? arow[q][b * BW + 1] : 0.0;
+                }
+            }
+            load_b(x, b);  // zero padded past n
+            mma(a, x);
+        }
+    };
+    if (S.aligned)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 
     // Add the W partial tiles in wave order; epilogue r = B - A x_new.
 #pragma unroll
@@ -303,6 +324,26 @@ hipError_t launch_resid_prep(int32_t kt, const RSys* sys, RState* st, int32_t co
         hipLaunchKernelGGL((k_resid_prep<32>), dim3((unsigned)bx, count), dim3(256), 0, s, sys, st);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// 16-byte word copy between any two device-visible buffers (descriptor
+// uploads from and outcome read-backs to pinned host memory).
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy16(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 16 != 0 || (uintptr_t)src % 16 != 0 || (uintptr_t)dst % 16 != 0)
+        return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks > 64) blocks = 64;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src,
+                       (uint4*)dst, n16);
     return hipGetLastError();
 }
 

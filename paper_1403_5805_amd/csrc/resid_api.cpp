@@ -94,27 +94,24 @@ jacobi_status run_resid(jacobi_ctx* c, int32_t count, const ResidItem* items, hi
         g.jobs += nj;
         g.max_xld = std::max(g.max_xld, S.xld);
     }
+    // Device layout [systems | job table | outcomes | job sums]; the first two
+    // are uploaded through the pinned stage, the outcomes come back through it.
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t sys_b = align(sizeof(RSys) * count), st_b = align(sizeof(RState) * count);
+    const size_t sys_b = align(sizeof(RSys) * count);
     const size_t job_b = align(sizeof(int32_t) * job_sys.size());
+    const size_t st_b = align(sizeof(RState) * count);
     const size_t parts_b = align(sizeof(double) * job_sys.size());
-    HIP_TRY(c->rmeta.ensure(sys_b + st_b + job_b + parts_b));
+    HIP_TRY(c->rmeta.ensure(sys_b + job_b + st_b + parts_b));
+    HIP_TRY(c->stage.ensure(sys_b + job_b + st_b));
     char* meta = (char*)c->rmeta.p;
     RSys* d_sys = (RSys*)meta;
-    RState* d_st = (RState*)(meta + sys_b);
-    int32_t* d_job = (int32_t*)(meta + sys_b + st_b);
-    double* d_parts = (double*)(meta + sys_b + st_b + job_b);
-    if (c->h_rst_cap < count) {
-        if (c->h_rst) hipHostFree(c->h_rst);
-        c->h_rst = nullptr;
-        c->h_rst_cap = 0;
-        const int cap = std::max(count, 64);
-        HIP_TRY(hipHostMalloc((void**)&c->h_rst, sizeof(RState) * cap, hipHostMallocDefault));
-        c->h_rst_cap = cap;
-    }
-    HIP_TRY(hipMemcpyAsync(d_sys, hs.data(), sizeof(RSys) * count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_job, job_sys.data(), sizeof(int32_t) * job_sys.size(),
-                           hipMemcpyHostToDevice, s));
+    int32_t* d_job = (int32_t*)(meta + sys_b);
+    RState* d_st = (RState*)(meta + sys_b + job_b);
+    double* d_parts = (double*)(meta + sys_b + job_b + st_b);
+    char* h = (char*)c->stage.h;
+    std::memcpy(h, hs.data(), sizeof(RSys) * count);
+    std::memcpy(h + sys_b, job_sys.data(), sizeof(int32_t) * job_sys.size());
+    HIP_TRY(launch_copy16(c->stage.d, meta, sys_b + job_b, s));
     for (const Group& g : groups) {
         HIP_TRY(launch_resid_prep(g.kt, d_sys + g.first, d_st + g.first, g.count, g.max_xld, s));
         RArgs a{};
@@ -124,9 +121,10 @@ jacobi_status run_resid(jacobi_ctx* c, int32_t count, const ResidItem* items, hi
         a.parts = d_parts + g.job0;
         HIP_TRY(launch_resid(g.kt, g.tiles, a, g.jobs, s));
     }
-    HIP_TRY(hipMemcpyAsync(c->h_rst, d_st, sizeof(RState) * count, hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_copy16(d_st, (char*)c->stage.d + sys_b + job_b, st_b, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int o = 0; o < count; ++o) out[order[o]] = c->h_rst[o];
+    const RState* hst = (const RState*)(h + sys_b + job_b);
+    for (int o = 0; o < count; ++o) out[order[o]] = hst[o];
     return JACOBI_OK;
 }
 

@@ -2,10 +2,11 @@
 //
 // Two worker threads per server:
 //   copy thread     admits queued requests while the HBM budget and the active
-//                   slots allow, allocates their device state from a
-//                   stream-ordered pool and copies A and B host -> device on
-//                   its own stream, so transfers overlap the sweeps of the
-//                   requests already on the device;
+//                   slots allow, places their device state in the server's
+//                   arena (slabs reserved once, reused as requests retire) and
+//                   copies A and B host -> device on its own stream, so
+//                   transfers overlap the sweeps of the requests already on
+//                   the device;
 //   compute thread  turns arrived requests into active ones (A_lo = round(A)
 //                   on the device, x = 0) and steps the whole active set: one
 //                   batched FP64 residual launch for every request (x += d
@@ -31,6 +32,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.h"
 #include "batch.h"
 #include "ctx.h"
 
@@ -79,6 +81,17 @@ struct Req {
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Arena slabs: 4 GiB (two of the largest requests of the size mix) unless a
+// request needs more; reserved with hipMalloc on the server's device.
+constexpr size_t kSlabBytes = (size_t)4 << 30;
+
+void* arena_slab_alloc(size_t bytes, void*) {
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void arena_slab_free(void* p, void*) { hipFree(p); }
+
 size_t footprint(int64_t n, int64_t k, int32_t lo, int64_t* ld_lo_out) {
     const int kp = kpad_of(k);
     const int64_t ld_lo = (n + 7) / 8 * 8;
@@ -116,6 +129,8 @@ struct jacobi_server {
     double t_first = -1.0, t_last = 0.0;
     std::vector<double> lat_e2e, lat_dev;
     bool copy_failed = false;
+    jac::Arena* arena = nullptr;  // device memory of the requests (guarded by mu)
+    uint64_t releases = 0;        // retirements so far (wakes an arena wait)
 };
 
 namespace {
@@ -141,26 +156,39 @@ void copy_loop(jacobi_server* s) {
     const bool trace = getenv("JACOBI_SERVE_TRACE") != nullptr;  // per-copy timing to stderr
     for (;;) {
         Req* q = nullptr;
+        void* p = nullptr;
+        double t_copy0 = 0.0;
         {
             std::unique_lock<std::mutex> g(s->mu);
-            s->cv_copy.wait(g, [&] {
-                if (s->stopping) return true;
-                if (s->queued.empty()) return false;
-                Req* h = s->queued.front();
-                return s->admitted_slots < s->cfg.max_active &&
-                       s->hbm_in_use + h->bytes <= s->cfg.hbm_budget_bytes;
-            });
-            if (s->stopping) return;
+            for (;;) {
+                s->cv_copy.wait(g, [&] {
+                    if (s->stopping) return true;
+                    if (s->queued.empty()) return false;
+                    Req* h = s->queued.front();
+                    return s->admitted_slots < s->cfg.max_active &&
+                           s->hbm_in_use + h->bytes <= s->cfg.hbm_budget_bytes;
+                });
+                if (s->stopping) return;
+                t_copy0 = now_s();
+                p = s->arena->alloc(s->queued.front()->bytes);
+                if (p) break;
+                if (s->arena->in_use() == 0) break;  // cannot be placed at all
+                // the free space is fragmented: wait for a retirement
+                const uint64_t gen = s->releases;
+                s->cv_copy.wait(g, [&] { return s->stopping || s->releases != gen; });
+            }
             q = s->queued.front();
             s->queued.pop_front();
+            if (!p) {
+                set_error("request of %zu bytes does not fit the device arena", q->bytes);
+                finish_locked(s, q, JACOBI_ERR_OUT_OF_MEMORY);
+                continue;
+            }
             s->admitted_slots += 1;
             s->hbm_in_use += q->bytes;
             s->hbm_peak = std::max(s->hbm_peak, s->hbm_in_use);
         }
-        // device state in one stream-ordered allocation
-        const double t_copy0 = now_s();
-        void* p = nullptr;
-        hipError_t e = hipMallocAsync(&p, q->bytes, s->s_copy);
+        hipError_t e = hipSuccess;
         const int64_t n = q->r.n, k = q->r.k;
         if (e == hipSuccess) {
             char* b = (char*)p;
@@ -206,12 +234,14 @@ void copy_loop(jacobi_server* s) {
             fprintf(stderr, "[serve] copy n=%lld k=%lld %.2f ms %.2f GB/s\n", (long long)n,
                     (long long)k, dt * 1e3, gb / dt);
         }
+        if (e != hipSuccess) hipStreamSynchronize(s->s_copy);  // nothing in flight before the free
         std::lock_guard<std::mutex> g(s->mu);
         if (e != hipSuccess) {
-            if (q->base) hipFreeAsync(q->base, s->s_copy);
+            s->arena->free(q->base, q->bytes);
             q->base = nullptr;
             s->hbm_in_use -= q->bytes;
             s->admitted_slots -= 1;
+            s->releases += 1;
             finish_locked(s, q, JACOBI_ERR_DEVICE);
             continue;
         }
@@ -235,12 +265,14 @@ void copy_out(jacobi_server* s, Req* q) {
                          s->s_comp);
 }
 
-// Release a request's device memory (after every use on the compute stream).
+// Release a request's device memory.  The compute stream has finished every
+// use of it (the step ends with a stream synchronisation).
 void release_locked(jacobi_server* s, Req* q) {
-    if (q->base) hipFreeAsync(q->base, s->s_comp);
+    s->arena->free(q->base, q->bytes);
     q->base = nullptr;
     s->hbm_in_use -= q->bytes;
     s->admitted_slots -= 1;
+    s->releases += 1;
     s->cv_copy.notify_all();
 }
 
@@ -440,18 +472,15 @@ jacobi_status jacobi_serve_create(const jacobi_serve_config* cfg, jacobi_server*
             hipMemGetInfo(&fr, &tot);
             c.hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
         }
-        // keep freed request memory in the stream-ordered pool
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, c.device) == hipSuccess) {
-            uint64_t thr = UINT64_MAX;
-            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-        }
         jacobi_server* s = new jacobi_server();
         s->cfg = c;
         s->ctx = ctx;
+        s->arena = new Arena(arena_slab_alloc, arena_slab_free, nullptr, kSlabBytes,
+                             (size_t)c.hbm_budget_bytes);
         if (hipStreamCreateWithFlags(&s->s_copy, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking) != hipSuccess) {
             jacobi_ctx_destroy(ctx);
+            delete s->arena;
             delete s;
             return JACOBI_ERR_DEVICE;
         }
@@ -606,13 +635,14 @@ jacobi_status jacobi_serve_destroy(jacobi_server* s) {
         for (auto& kv : s->all) {
             Req* q = kv.second;
             if (q->base) {
-                hipFreeAsync(q->base, s->s_comp);
+                s->arena->free(q->base, q->bytes);
                 q->base = nullptr;
             }
             if (q->status == JACOBI_PENDING) finish_locked(s, q, JACOBI_CANCELLED);
         }
     }
-    hipStreamSynchronize(s->s_comp);
+    delete s->arena;  // both streams are idle: the slabs go back to the device
+    s->arena = nullptr;
     for (auto& kv : s->all) delete kv.second;
     s->all.clear();
     hipStreamDestroy(s->s_copy);

@@ -1,5 +1,5 @@
 // Test driver for the batched workgroup planner (paper_1403_5805_amd/csrc/plan.cpp).
-// Reads "capacity waves unroll bw count n_0 ... n_{count-1}" from stdin and
+// Reads "capacity tpp unroll bw count n_0 ... n_{count-1}" from stdin and
 // prints the plan: "grid G", one "nwg i v" line per system and one
 // "wg g sys rank r0 r1" line per job.  Built with g++; no GPU involved.
 #include <cstdio>
@@ -8,15 +8,15 @@
 #include "../paper_1403_5805_amd/csrc/plan.h"
 
 int main() {
-    int capacity, waves, unroll, bw, count;
-    if (std::scanf("%d %d %d %d %d", &capacity, &waves, &unroll, &bw, &count) != 5) return 2;
+    int capacity, tpp, unroll, bw, count;
+    if (std::scanf("%d %d %d %d %d", &capacity, &tpp, &unroll, &bw, &count) != 5) return 2;
     std::vector<int64_t> n(count);
     for (int i = 0; i < count; ++i) {
         long long v;
         if (std::scanf("%lld", &v) != 1) return 2;
         n[i] = v;
     }
-    const jac::Plan p = jac::make_plan(n, capacity, waves, unroll, bw);
+    const jac::Plan p = jac::make_plan(n, capacity, tpp, unroll, bw);
     std::printf("grid %d\n", p.grid);
     for (int i = 0; i < count; ++i) std::printf("nwg %d %d\n", i, p.nwg[i]);
     for (int g = 0; g < p.grid; ++g)

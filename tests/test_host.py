@@ -251,8 +251,8 @@ def plan_exe(tmp_path_factory):
     return str(exe)
 
 
-def _plan(exe, ns, capacity, waves=4, unroll=2, bw=16):
-    inp = f"{capacity} {waves} {unroll} {bw} {len(ns)} " + " ".join(str(int(v)) for v in ns)
+def _plan(exe, ns, capacity, tpp=2, unroll=4, bw=64):
+    inp = f"{capacity} {tpp} {unroll} {bw} {len(ns)} " + " ".join(str(int(v)) for v in ns)
     out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True).stdout
     grid, nwg, wgs = 0, {}, {}
     for ln in out.splitlines():
@@ -315,3 +315,22 @@ def test_planner_balances_the_batched_workload(plan_exe):
     assert max(nwg.values()) >= 2
     load = [sum((r1 - r0) * ns[s] for s, _, r0, r1 in jobs) for jobs in wgs.values()]
     assert max(load) <= 2.0 * (sum(load) / len(load)) + 16 * 4096
+
+
+# ---- serving arena -----------------------------------------------------------
+
+def test_serving_arena_invariants(tmp_path):
+    """Best-fit arena of the serving engine on random alloc/free sequences:
+    aligned, disjoint blocks inside reserved slabs; the reservation limit is
+    kept; a refusal only when no free block fits; freeing everything
+    coalesces each slab back into one block and the space is reused; no slab
+    outlives the arena."""
+    exe = tmp_path / "arena_check"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror",
+                    os.path.join(ROOT, "tests", "arena_check.cpp"),
+                    os.path.join(PKG, "csrc", "arena.cpp"), "-o", str(exe)], check=True)
+    for seed, ops, limit_mb, slab_mb in [(1, 20000, 4096, 1024), (2, 20000, 4096, 1024),
+                                         (3, 5000, 64, 4096), (4, 20000, 1024, 16)]:
+        out = subprocess.run([str(exe), str(seed), str(ops), str(limit_mb), str(slab_mb)],
+                             capture_output=True, text=True)
+        assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
