@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -42,15 +43,22 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         nmax = std::max(nmax, items[i].n);
     }
     const int kt = kmax <= 16 ? 16 : 32;
-    const int capacity = batched_max_grid(a_dtype, kt, c->num_cus);
+    // Kernel shape: many systems (at least one per four CUs) pack better on
+    // the wide shape, a few large ones stream better on the deep one.
+    int variant = count * 4 >= c->num_cus ? 0 : 1;
+    if (const char* env = getenv("JACOBI_BATCHED_SHAPE")) {
+        if (!strcmp(env, "wide")) variant = 0;
+        if (!strcmp(env, "deep")) variant = 1;
+    }
+    const int capacity = batched_max_grid(a_dtype, kt, variant, c->num_cus);
     if (capacity < 1) {
         set_error("batched kernel unavailable for this dtype");
         return JACOBI_ERR_INVALID_ARG;
     }
     std::vector<int64_t> ns(count);
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
-    Plan plan = make_plan(ns, capacity, batched_tiles_per_pass(a_dtype, kt), batched_unroll(a_dtype),
-                          batched_block_cols(a_dtype));
+    Plan plan = make_plan(ns, capacity, batched_tiles_per_pass(a_dtype, kt, variant),
+                          batched_unroll(a_dtype), batched_block_cols(a_dtype));
     if (plan.grid > capacity) {
         // a cooperative launch needs every workgroup resident at once
         set_error("batched plan of %d workgroups exceeds the resident grid %d", plan.grid,
@@ -141,7 +149,7 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         rate_khz <= 0)
         rate_khz = 100000;
     ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
-    if (plan.grid > 0) HIP_TRY(launch_batched(a_dtype, kt, ba, plan.grid, s));
+    if (plan.grid > 0) HIP_TRY(launch_batched(a_dtype, kt, variant, ba, plan.grid, s));
     HIP_TRY(hipEventRecord(c->bev_end, s));
     HIP_TRY(launch_copy16(d_st, (char*)c->stage.d + up_b, st_b, s));
     HIP_TRY(hipStreamSynchronize(s));

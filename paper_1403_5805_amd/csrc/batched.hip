@@ -156,8 +156,9 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 //   W   waves per workgroup (they split the columns of every tile)
 //   TPW 16-row tiles per pass (they share every B operand load)
 //   U   column blocks per pipeline stage (two stages in flight)
-template <typename TA, int KT, int W, int TPW, int U>
-__global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
+//   MINB workgroups per CU the register budget is sized for
+template <typename TA, int KT, int W, int TPW, int U, int MINB>
+__global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
     constexpr int VEC = 16 / (int)sizeof(TA);  // A values per 16-byte lane load
     constexpr int BW = 4 * VEC;                // columns of one A block (16 or 32)
     constexpr int NT = KT / 16;                // 16-column output tiles
@@ -168,7 +169,8 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
     __shared__ uint32_t s_flag;
     __shared__ double s_delta;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block tests stay scalar
     const int grp = lane >> 4, li = lane & 15;
 
     for (int jb = p.job_off[blockIdx.x]; jb < p.job_off[blockIdx.x + 1]; ++jb) {
@@ -201,70 +203,87 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
             float* xout = (sweep & 1) ? S.buf1 : S.buf0;
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * TPW) {
-                int64_t rt[TPW];
-                gptr<TA> arow[TPW];
+            gptr<float> xrow[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
+            // Row pointers of the pass starting at row pr.  Rows past the job
+            // (a short last pass) re-read the job's last row, which the cache
+            // serves, and are discarded.
+            auto rows_of = [&](gptr<TA> (&rows)[TPW], int64_t pr) {
 #pragma unroll
                 for (int q = 0; q < TPW; ++q) {
-                    rt[q] = pr + 16 * q;
-                    int64_t ri = rt[q] + li;
-                    // rows past the job (a short last pass): re-read the
-                    // job's last row, which the cache serves, and discard
+                    int64_t ri = pr + 16 * q + li;
                     if (ri >= job.r1) ri = job.r1 - 1;
-                    arow[q] = gbl(A + ri * S.lda + VEC * grp);
+                    rows[q] = gbl(A + ri * S.lda + VEC * grp);
                 }
-                gptr<float> xrow[NT];
+            };
+            auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
+#pragma unroll
+                    for (int sg = 0; sg < NS; ++sg)
+                        bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
+            };
+            // Loads of U blocks starting at this wave's block t0.
+            auto issue = [&](const gptr<TA> (&rows)[TPW], u32x4 (&v)[U][TPW],
+                             f32x4 (&bx)[U][NT][NS], int64_t t0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t b = wave + W * (t0 + u);
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q)
+                        v[u][q] = __builtin_nontemporal_load((gptr<u32x4>)(rows[q] + b * BW));
+                    load_b(bx[u], b);
+                }
+            };
+            // First pipeline stage of the next pass, loaded while the current
+            // pass finishes its reduction and epilogue.
+            u32x4 v0[U][TPW];
+            f32x4 b0[U][NT][NS];
+            bool preloaded = false;
+            gptr<TA> arow[TPW];
+            rows_of(arow, job.r0);
+            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * TPW) {
+                int64_t rt[TPW];
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) rt[q] = pr + 16 * q;
                 f32x4 acc[TPW][NT];
 #pragma unroll
                 for (int q = 0; q < TPW; ++q)
 #pragma unroll
                     for (int t = 0; t < NT; ++t) acc[q][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-                auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-#pragma unroll
-                        for (int sg = 0; sg < NS; ++sg)
-                            bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
-                };
                 // MFMAs of one A block (the TPW tiles share the B operand).
                 auto mfma_block = [&](float (&a)[TPW][VEC], const f32x4 (&bx)[NT][NS], int64_t b) {
+                    // Tile q's diagonal lies in block rt[q] / BW (BW is 16 or
+                    // 32, tiles start at multiples of 16): only that block,
+                    // a wave-uniform test, masks the lane's element dpos.
 #pragma unroll
                     for (int q = 0; q < TPW; ++q) {
-                        // Mask the diagonal without a branch: the lane's row
-                        // rt + li sits at element dpos of its load (rows and
-                        // columns are below 2^31).
-                        const int dpos = (int)rt[q] - (int)(b * BW) + li - VEC * grp;
+                        if (b == rt[q] / BW) {
+                            const int dpos = (int)(rt[q] - b * BW) + li - VEC * grp;
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
+                            for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
+                        }
+                    }
+                    // Consecutive MFMAs update different accumulators.
 #pragma unroll
-                        for (int sg = 0; sg < NS; ++sg)
+                    for (int sg = 0; sg < NS; ++sg)
 #pragma unroll
-                            for (int t = 0; t < NT; ++t)
+                        for (int r = 0; r < 4; ++r)
 #pragma unroll
-                                for (int r = 0; r < 4; ++r)
+                            for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                                for (int t = 0; t < NT; ++t)
                                     acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                         a[q][4 * sg + r], bx[t][sg][r], acc[q][t], 0, 0, 0);
-                    }
                 };
                 // Vector-loadable blocks: two pipeline stages of U blocks; the
                 // loads of one stage are in flight during the MFMAs of the other.
                 if (nfull > 0) {
-                    u32x4 v0[U][TPW], v1[U][TPW];
-                    f32x4 b0[U][NT][NS], b1[U][NT][NS];
-                    auto issue = [&](u32x4 (&v)[U][TPW], f32x4 (&bx)[U][NT][NS], int64_t t0) {
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int64_t b = wave + W * (t0 + u);
-#pragma unroll
-                            for (int q = 0; q < TPW; ++q)
-                                v[u][q] = __builtin_nontemporal_load((gptr<u32x4>)(arow[q] + b * BW));
-                            load_b(bx[u], b);
-                        }
-                    };
+                    u32x4 v1[U][TPW];
+                    f32x4 b1[U][NT][NS];
                     auto consume = [&](u32x4 (&v)[U][TPW], f32x4 (&bx)[U][NT][NS], int64_t t0) {
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
@@ -276,20 +295,20 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                     };
                     // The scheduling barriers keep the compiler from sinking
                     // the loads below the MFMAs that should hide them.
-                    issue(v0, b0, 0);
+                    if (!preloaded) issue(arow, v0, b0, 0);
                     int64_t t = 0;
                     for (; t + 3 * U <= nfull; t += 2 * U) {
-                        issue(v1, b1, t + U);
+                        issue(arow, v1, b1, t + U);
                         __builtin_amdgcn_sched_barrier(0);
                         consume(v0, b0, t);
                         __builtin_amdgcn_sched_barrier(0);
-                        issue(v0, b0, t + 2 * U);
+                        issue(arow, v0, b0, t + 2 * U);
                         __builtin_amdgcn_sched_barrier(0);
                         consume(v1, b1, t + U);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     if (t + 2 * U <= nfull) {
-                        issue(v1, b1, t + U);
+                        issue(arow, v1, b1, t + U);
                         __builtin_amdgcn_sched_barrier(0);
                         consume(v0, b0, t);
                         __builtin_amdgcn_sched_barrier(0);
@@ -297,7 +316,15 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                     } else {
                         consume(v0, b0, t);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+                // Start the next pass's first stage now (A and the iterate do
+                // not change within a sweep).
+                gptr<TA> arow_next[TPW];
+                const bool more = pr + 16 * TPW < job.r1;
+                if (more) rows_of(arow_next, pr + 16 * TPW);
+                preloaded = more && nfull > 0;
+                if (preloaded) issue(arow_next, v0, b0, 0);
                 // Remaining blocks of this wave (ragged tail, or every block of
                 // rows that are not 16-byte aligned).
                 for (int64_t b = wave + W * nfull; b < nb; b += W) {
@@ -353,6 +380,10 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
                     }
                 }
                 __syncthreads();  // red is reused by the next pass
+                if (more) {
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q) arow[q] = arow_next[q];
+                }
             }
             // ---- workgroup reduction of the distance statistics
             dmax = wmax(dmax);
@@ -466,34 +497,41 @@ __global__ __launch_bounds__(W * 64, 2) void k_batched(BatchArgs p) {
 constexpr int kBW = 4;   // waves per workgroup
 constexpr int kBU = 2;   // A blocks per pipeline stage
 
-// 16-row tiles per pass: more tiles share each B operand load; 32 output
-// columns, or BF16 blocks (8 values per load), leave registers for fewer.
+// Two shapes of the kernel:
+//   wide  two workgroups per CU; 4 tiles per pass for FP32 with <= 16 columns,
+//         else 2 (registers).  Many small systems: more workgroups to pack.
+//   deep  one workgroup per CU (the register file doubles, accumulators move
+//         to AGPRs) and 4 tiles per pass everywhere, so each B operand load
+//         serves 4 tiles.  Few large systems: less L2 traffic per A byte.
 template <typename TA>
-constexpr int tiles_per_pass(int kt) {
-    return (kt <= 16 && sizeof(TA) == 4) ? 4 : 2;
+constexpr int tiles_per_pass(int kt, int variant) {
+    return (variant == 1 || (kt <= 16 && sizeof(TA) == 4)) ? 4 : 2;
 }
 
 // Shape parameters seen by the host planner: tiles per pass and the columns
 // one wave covers per pipeline round trip.
-int batched_tiles_per_pass(int32_t a_dtype, int32_t kt) {
-    return a_dtype == 1 ? tiles_per_pass<float>(kt) : tiles_per_pass<bf16_t>(kt);
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant) {
+    return a_dtype == 1 ? tiles_per_pass<float>(kt, variant) : tiles_per_pass<bf16_t>(kt, variant);
 }
 int batched_unroll(int32_t) { return 2 * kBU; }
 int batched_block_cols(int32_t a_dtype) { return kBW * (a_dtype == 1 ? 16 : 32); }
 
 template <typename TA, int KT>
-static const void* batched_fn() {
-    return (const void*)k_batched<TA, KT, kBW, tiles_per_pass<TA>(KT), kBU>;
+static const void* batched_fn(int variant) {
+    if (variant == 1) return (const void*)k_batched<TA, KT, kBW, tiles_per_pass<TA>(KT, 1), kBU, 1>;
+    return (const void*)k_batched<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2>;
 }
 
-static const void* pick(int32_t a_dtype, int32_t kt) {
-    if (a_dtype == 1) return kt <= 16 ? batched_fn<float, 16>() : batched_fn<float, 32>();
-    if (a_dtype == 2) return kt <= 16 ? batched_fn<bf16_t, 16>() : batched_fn<bf16_t, 32>();
+static const void* pick(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 1)
+        return kt <= 16 ? batched_fn<float, 16>(variant) : batched_fn<float, 32>(variant);
+    if (a_dtype == 2)
+        return kt <= 16 ? batched_fn<bf16_t, 16>(variant) : batched_fn<bf16_t, 32>(variant);
     return nullptr;
 }
 
-int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus) {
-    const void* fn = pick(a_dtype, kt);
+int batched_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus) {
+    const void* fn = pick(a_dtype, kt, variant);
     if (!fn) return 0;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, 0) != hipSuccess ||
@@ -515,9 +553,9 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
     return hipGetLastError();
 }
 
-hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int grid,
+hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
                           hipStream_t s) {
-    const void* fn = pick(a_dtype, kt);
+    const void* fn = pick(a_dtype, kt, variant);
     if (!fn) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* args[] = {&copy};

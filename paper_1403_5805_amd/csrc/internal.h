@@ -166,9 +166,9 @@ struct BatchArgs {
 
 hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,
                                 int32_t count, int64_t max_n, hipStream_t s);
-hipError_t launch_batched(int32_t a_dtype, int32_t kt, const BatchArgs& a, int grid,
+hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
                           hipStream_t s);
-int batched_max_grid(int32_t a_dtype, int32_t kt, int num_cus);
+int batched_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 
 // ---------------------------------------------------------------------------
 // Batched FP64 residual pass (resid.hip): for many systems at once,
@@ -222,7 +222,7 @@ int resid_tiles(int32_t kt, int64_t n, int num_cus);
 hipError_t launch_resid_prep(int32_t kt, const RSys* sys, RState* st, int32_t count,
                              int64_t max_xld, hipStream_t s);
 hipError_t launch_resid(int32_t kt, int32_t tiles, const RArgs& a, int32_t jobs, hipStream_t s);
-int batched_tiles_per_pass(int32_t a_dtype, int32_t kt);
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant);
 int batched_unroll(int32_t a_dtype);
 int batched_block_cols(int32_t a_dtype);
 

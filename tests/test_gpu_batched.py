@@ -74,6 +74,30 @@ def test_batch_invariance_bitwise(jac):
     assert torch.equal(X, xs[0]) and info["iterations"] == infos[0]["iterations"]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
+    """The wide (two workgroups per CU) and deep (one per CU, four tiles per
+    pass) kernel shapes sum every element in the same order: bitwise the
+    same X and counts."""
+    import torch
+    shapes = [(700, 32), (64, 5), (2048, 16), (300, 1), (1500, 9)]
+    sysl = []
+    for idx, (n, k) in enumerate(shapes):
+        A32, _, B32 = _sys32(n, k, 950 + idx)
+        A = dev(A32)
+        sysl.append((A.to(torch.bfloat16) if dtype == "bf16" else A, dev(B32)))
+    out = {}
+    for shape in ("wide", "deep"):
+        monkeypatch.setenv("JACOBI_BATCHED_SHAPE", shape)
+        say("batched shape", shape, dtype)
+        out[shape] = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    monkeypatch.delenv("JACOBI_BATCHED_SHAPE")
+    for i in range(len(shapes)):
+        assert torch.equal(out["wide"][0][i], out["deep"][0][i]), shapes[i]
+        assert out["wide"][1][i]["iterations"] == out["deep"][1][i]["iterations"]
+        assert out["wide"][1][i]["status"] == jac.OK
+
+
 def test_failures_isolated(jac):
     """A zero diagonal / NaN right-hand side fails only its own system; its X
     is untouched and its neighbours are bitwise unaffected."""
