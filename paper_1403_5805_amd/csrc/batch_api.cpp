@@ -57,8 +57,10 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     }
     std::vector<int64_t> ns(count);
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
+    int max_split = 1 << 30;
+    if (const char* env = getenv("JACOBI_BATCHED_MAXSPLIT")) max_split = atoi(env);
     Plan plan = make_plan(ns, capacity, batched_tiles_per_pass(a_dtype, kt, variant),
-                          batched_unroll(a_dtype), batched_block_cols(a_dtype));
+                          batched_unroll(a_dtype), batched_block_cols(a_dtype), max_split);
     if (plan.grid > capacity) {
         // a cooperative launch needs every workgroup resident at once
         set_error("batched plan of %d workgroups exceeds the resident grid %d", plan.grid,
@@ -78,15 +80,17 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
     const size_t job_b = align(sizeof(BJob) * std::max<size_t>(1, plan.jobs.size()));
     const size_t off_b = align(sizeof(int32_t) * plan.job_off.size());
+    const size_t q_b = align(sizeof(int32_t) * std::max<size_t>(1, plan.queue.size()) + 16);
     const size_t parts_b = align(sizeof(double) * 2 * (size_t)count * plan.max_nwg);
     HIP_TRY(c->bws.ensure(ws));
-    HIP_TRY(c->bmeta.ensure(sys_b + st_b + job_b + off_b + parts_b));
+    HIP_TRY(c->bmeta.ensure(sys_b + st_b + job_b + off_b + q_b + parts_b));
     char* meta = (char*)c->bmeta.p;
     BSys* d_sys = (BSys*)meta;
     BState* d_st = (BState*)(meta + sys_b);
     BJob* d_jobs = (BJob*)(meta + sys_b + st_b);
     int32_t* d_off = (int32_t*)(meta + sys_b + st_b + job_b);
-    double* d_parts = (double*)(meta + sys_b + st_b + job_b + off_b);
+    char* d_q = meta + sys_b + st_b + job_b + off_b;  // [head (16 bytes) | queue]
+    double* d_parts = (double*)(meta + sys_b + st_b + job_b + off_b + q_b);
 
     std::vector<BSys> hs(count);
     std::vector<BState> hst(count);
@@ -124,7 +128,7 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     }
     // Descriptors, initial states, job table and offsets go up through the
     // pinned stage in one copy kernel; the states come back the same way.
-    const size_t up_b = sys_b + st_b + job_b + off_b;
+    const size_t up_b = sys_b + st_b + job_b + off_b + q_b;
     HIP_TRY(c->stage.ensure(up_b + st_b));
     char* h = (char*)c->stage.h;
     std::memcpy(h, hs.data(), sizeof(BSys) * count);
@@ -133,6 +137,10 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         std::memcpy(h + sys_b + st_b, plan.jobs.data(), sizeof(BJob) * plan.jobs.size());
     std::memcpy(h + sys_b + st_b + job_b, plan.job_off.data(),
                 sizeof(int32_t) * plan.job_off.size());
+    std::memset(h + sys_b + st_b + job_b + off_b, 0, 16);  // queue head
+    if (!plan.queue.empty())
+        std::memcpy(h + sys_b + st_b + job_b + off_b + 16, plan.queue.data(),
+                    sizeof(int32_t) * plan.queue.size());
     HIP_TRY(launch_copy16(c->stage.d, meta, up_b, s));
     HIP_TRY(hipEventRecord(c->bev_begin, s));
     HIP_TRY(launch_batched_setup(a_dtype, kt, d_sys, d_st, count, nmax, s));
@@ -142,6 +150,9 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     ba.jobs = d_jobs;
     ba.job_off = d_off;
     ba.parts = d_parts;
+    ba.queue_head = (uint32_t*)d_q;
+    ba.queue = (const int32_t*)(d_q + 16);
+    ba.queue_len = (int32_t)plan.queue.size();
     ba.max_nwg = plan.max_nwg;
     ba.count = count;
     int rate_khz = 100000;

@@ -173,8 +173,30 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block tests stay scalar
     const int grp = lane >> 4, li = lane & 15;
 
-    for (int jb = p.job_off[blockIdx.x]; jb < p.job_off[blockIdx.x + 1]; ++jb) {
-        const BJob job = p.jobs[jb];
+    __shared__ int32_t s_next;
+    int jb = p.job_off[blockIdx.x];
+    const int jend = p.job_off[blockIdx.x + 1];
+    for (;;) {
+        // The workgroup's fixed jobs (shares of split systems), then whole
+        // systems from the queue until it runs dry.
+        BJob job;
+        if (jb < jend) {
+            job = p.jobs[jb++];
+        } else {
+            __syncthreads();
+            if (tid == 0)
+                s_next = p.queue_len > 0 ? (int32_t)__hip_atomic_fetch_add(
+                                               p.queue_head, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                                         : INT32_MAX;
+            __syncthreads();
+            const int32_t qi = s_next;
+            if (qi >= p.queue_len) break;
+            job.sys = p.queue[qi];
+            job.rank = 0;
+            job.r0 = 0;
+            job.r1 = (int32_t)p.sys[job.sys].n;
+        }
         const BSys S = p.sys[job.sys];
         BState* st = &p.st[job.sys];
         if (__hip_atomic_load(&st->bad_diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=

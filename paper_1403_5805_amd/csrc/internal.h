@@ -159,6 +159,9 @@ struct BatchArgs {
     const BJob* jobs;
     const int32_t* job_off;   // [grid + 1]: jobs of workgroup g are [job_off[g], job_off[g+1])
     double* parts;            // [2][count][max_nwg] L2 partial sums
+    const int32_t* queue;     // systems run whole by whichever workgroup is free
+    uint32_t* queue_head;     // next queue entry (zero at launch)
+    int32_t queue_len;
     int32_t max_nwg;
     int32_t count;
     int64_t spin_limit;       // wall-clock ticks (100 MHz) before a barrier wait gives up

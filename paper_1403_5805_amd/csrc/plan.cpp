@@ -3,8 +3,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <functional>
-#include <queue>
 #include <utility>
 
 namespace jac {
@@ -19,12 +17,13 @@ static double job_cost(int64_t n, int64_t rows, int tpp, int unroll, int bw) {
     return passes * (1.0 + std::ceil(blocks / unroll)) + 1.0;
 }
 
-// Split big systems over several workgroups and pack small systems whole
-// into the remaining workgroups (longest-processing-time first), both by the
-// modelled sweep time above.  A workgroup that shares a system with others
+// Split big systems over several workgroups (by the modelled sweep time
+// above) and queue the small ones, largest first, for whichever workgroup is
+// free.  A workgroup that shares a system with others
 // owns nothing else, so barrier waits only involve workgroups that are certain
 // to arrive.
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw) {
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw,
+               int max_split) {
     Plan p;
     const int count = (int)n.size();
     p.nwg.assign(count, 1);
@@ -46,6 +45,7 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
         int want = (int)std::lround(cost[i] / target);
         // no share smaller than one full pass of tiles
         want = (int)std::min<int64_t>(want, (tiles + tpp - 1) / tpp);
+        want = std::min(want, std::max(1, max_split));
         if (want >= 2) {
             p.nwg[i] = want;
             big.push_back(i);
@@ -85,31 +85,17 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
             wg_jobs.push_back({j});
         }
     }
-    const int bins = std::max(small.empty() ? 0 : 1,
+    // Systems that run whole are not bound to workgroups: they wait in a
+    // queue, largest first, and every workgroup takes the next one when it
+    // is free (its own split share done, or none).  Workgroups set aside for
+    // the queue carry no fixed job.
+    const int pool = std::max(small.empty() ? 0 : 1,
                               std::min((int)small.size(), capacity - (int)wg_jobs.size()));
-    if (bins > 0) {
-        std::sort(small.begin(), small.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        using Item = std::pair<double, int>;
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-        const size_t base = wg_jobs.size();
-        wg_jobs.resize(base + bins);
-        for (int b = 0; b < bins; ++b) heap.push({0.0, b});
-        for (int i : small) {
-            Item it = heap.top();
-            heap.pop();
-            BJob j;
-            j.sys = i;
-            j.rank = 0;
-            j.r0 = 0;
-            j.r1 = (int32_t)n[i];
-            wg_jobs[base + it.second].push_back(j);
-            it.first += cost[i];
-            heap.push(it);
-        }
-    }
+    std::stable_sort(small.begin(), small.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int i : small) p.queue.push_back(i);
+    wg_jobs.resize(wg_jobs.size() + pool);
     p.job_off.push_back(0);
     for (auto& v : wg_jobs) {
-        if (v.empty()) continue;
         for (auto& j : v) p.jobs.push_back(j);
         p.job_off.push_back((int32_t)p.jobs.size());
     }

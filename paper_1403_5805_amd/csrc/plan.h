@@ -16,21 +16,27 @@ struct BJob {
     int32_t r1;
 };
 
-// Workgroup plan: jobs of workgroup g are jobs[job_off[g] .. job_off[g+1]).
+// Workgroup plan: fixed jobs of workgroup g are jobs[job_off[g] ..
+// job_off[g+1]); afterwards every workgroup takes whole systems from `queue`
+// (an atomic head) until it is empty.
 struct Plan {
     std::vector<int> nwg;        // workgroups per system
     std::vector<BJob> jobs;
     std::vector<int32_t> job_off;
+    std::vector<int32_t> queue;  // systems run whole, largest first
     int grid = 0;
     int max_nwg = 1;
 };
 
 // Plan `n.size()` systems (sizes n[i]) onto at most `capacity` co-resident
 // workgroups that sweep `tpp` 16-row tiles per pass and cover `bw` columns of
-// them per load, `unroll` loads per round trip.  Guarantees: grid <= capacity; the jobs of system i cover its
-// rows [0, n[i]) exactly once, split at multiples of 16 rows; a system split
-// over nwg[i] >= 2 workgroups has one job of each rank 0..nwg[i]-1, and a
-// workgroup holding such a job holds nothing else.
-Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw);
+// them per load, `unroll` loads per round trip.  Guarantees: grid <= capacity;
+// every system is either split over nwg[i] >= 2 workgroups, one fixed job of
+// each rank 0..nwg[i]-1 covering its rows [0, n[i]) exactly once at multiples
+// of 16 rows, each on a workgroup with no other fixed job, or listed once in
+// the queue (nwg[i] = 1) in order of decreasing modelled cost.  No system is
+// split over more than max_split workgroups.
+Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw,
+               int max_split = 1 << 30);
 
 }  // namespace jac

@@ -1,7 +1,8 @@
 // Test driver for the batched workgroup planner (paper_1403_5805_amd/csrc/plan.cpp).
 // Reads "capacity tpp unroll bw count n_0 ... n_{count-1}" from stdin and
-// prints the plan: "grid G", one "nwg i v" line per system and one
-// "wg g sys rank r0 r1" line per job.  Built with g++; no GPU involved.
+// prints the plan: "grid G", one "nwg i v" line per system, one
+// "wg g sys rank r0 r1" line per fixed job and one "q sys" line per queue
+// entry, in queue order.  Built with g++; no GPU involved.
 #include <cstdio>
 #include <vector>
 
@@ -23,5 +24,6 @@ int main() {
         for (int j = p.job_off[g]; j < p.job_off[g + 1]; ++j)
             std::printf("wg %d %d %d %d %d\n", g, p.jobs[j].sys, p.jobs[j].rank, p.jobs[j].r0,
                         p.jobs[j].r1);
+    for (int32_t q : p.queue) std::printf("q %d\n", q);
     return 0;
 }

@@ -254,22 +254,26 @@ def plan_exe(tmp_path_factory):
 def _plan(exe, ns, capacity, tpp=2, unroll=4, bw=64):
     inp = f"{capacity} {tpp} {unroll} {bw} {len(ns)} " + " ".join(str(int(v)) for v in ns)
     out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True).stdout
-    grid, nwg, wgs = 0, {}, {}
+    grid, nwg, wgs, queue = 0, {}, {}, []
     for ln in out.splitlines():
         p = ln.split()
         if p[0] == "grid":
             grid = int(p[1])
         elif p[0] == "nwg":
             nwg[int(p[1])] = int(p[2])
+        elif p[0] == "q":
+            queue.append(int(p[1]))
         else:
             g, s, r, r0, r1 = map(int, p[1:])
             wgs.setdefault(g, []).append((s, r, r0, r1))
-    return grid, nwg, wgs
+    return grid, nwg, wgs, queue
 
 
-def _check_plan(ns, capacity, grid, nwg, wgs):
+def _check_plan(ns, capacity, grid, nwg, wgs, queue):
     assert 0 <= grid <= capacity
-    assert sorted(wgs) == list(range(grid))   # no empty workgroup
+    assert all(0 <= g < grid for g in wgs)
+    if len(wgs) < grid:
+        assert queue, "a workgroup without fixed jobs only serves the queue"
     rows = {i: [] for i in range(len(ns))}
     ranks = {i: [] for i in range(len(ns))}
     for g, jobs in wgs.items():
@@ -277,15 +281,27 @@ def _check_plan(ns, capacity, grid, nwg, wgs):
             rows[s].append((r0, r1))
             ranks[s].append(r)
             assert r0 % 16 == 0 and r0 < r1 <= ns[s]
-            if nwg[s] >= 2:
-                assert len(jobs) == 1, "a split system's workgroup holds nothing else"
+            assert nwg[s] >= 2, "fixed jobs are shares of split systems"
+            assert len(jobs) == 1, "a split system's workgroup holds nothing else"
+    assert len(queue) == len(set(queue))
     for i, n in enumerate(ns):
+        if i in queue:
+            assert nwg[i] == 1 and not rows[i]
+            continue
+        assert nwg[i] >= 2
         spans = sorted(rows[i])
         assert spans and spans[0][0] == 0 and spans[-1][1] == n
         for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
             assert a1 == b0
         assert sorted(ranks[i]) == list(range(nwg[i]))
-        assert 1 <= nwg[i] <= (n + 15) // 16
+        assert nwg[i] <= (n + 15) // 16
+    # the queue is ordered by decreasing modelled cost: passes of tiles times
+    # load round trips per pass (the planner's model, tpp=2, unroll=4, bw=64)
+    def cost(n):
+        passes = -(-(-(-n // 16)) // 2)
+        return passes * (1 + -(-(-(-n // 64)) // 4)) + 1
+    qc = [cost(int(ns[i])) for i in queue]
+    assert qc == sorted(qc, reverse=True)
 
 
 def test_planner_invariants(plan_exe):
@@ -300,21 +316,24 @@ def test_planner_invariants(plan_exe):
         ns = np.exp(rng.uniform(np.log(1), np.log(20000), count)).astype(int) + 1
         cases.append((list(ns), int(rng.integers(1, 1024))))
     for ns, cap in cases:
-        grid, nwg, wgs = _plan(plan_exe, ns, cap)
-        _check_plan(ns, cap, grid, nwg, wgs)
+        grid, nwg, wgs, queue = _plan(plan_exe, ns, cap)
+        _check_plan(ns, cap, grid, nwg, wgs, queue)
 
 
-def test_planner_balances_the_batched_workload(plan_exe):
+def test_planner_on_the_batched_workload(plan_exe):
     """256 systems with n log-uniform in [256, 4096] on 512 resident
-    workgroups: big systems are split, and no workgroup carries more than
-    twice the average modelled load."""
+    workgroups: the largest systems are split, each share at least one full
+    pass of tiles, and the rest wait in the queue, largest first."""
     rng = np.random.default_rng(7)
     ns = np.exp(rng.uniform(np.log(256), np.log(4096), 256)).astype(int)
-    grid, nwg, wgs = _plan(plan_exe, ns, 512)
-    _check_plan(list(ns), 512, grid, nwg, wgs)
-    assert max(nwg.values()) >= 2
-    load = [sum((r1 - r0) * ns[s] for s, _, r0, r1 in jobs) for jobs in wgs.values()]
-    assert max(load) <= 2.0 * (sum(load) / len(load)) + 16 * 4096
+    grid, nwg, wgs, queue = _plan(plan_exe, ns, 512)
+    _check_plan(list(ns), 512, grid, nwg, wgs, queue)
+    split = [i for i in range(len(ns)) if nwg[i] > 1]
+    assert split and queue
+    assert min(ns[i] for i in split) >= max(ns[i] for i in queue) // 2
+    for g, jobs in wgs.items():
+        for s, r, r0, r1 in jobs:
+            assert r1 - r0 >= 32 or r1 == ns[s]
 
 
 # ---- serving arena -----------------------------------------------------------
