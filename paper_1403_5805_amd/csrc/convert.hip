@@ -1,0 +1,130 @@
+// FP64 -> FP32 / BF16 copy of A for the reduced-precision sweeps of the
+// refinement (round to nearest, ties to even, from FP64 in one rounding).
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace jac {
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
+    if (isnan(x)) return (uint16_t)0x7fc0u;
+    const double ax = fabs(x);
+    const uint32_t sign = (x < 0.0 || (x == 0.0 && signbit(x))) ? 0x8000u : 0u;
+    double r;
+    if (ax < 0x1.0p-126) {
+        // subnormal bf16 range: the quantum is 2^-133
+        r = __builtin_rint(ax * 0x1.0p133) * 0x1.0p-133;
+    } else {
+        // keep 8 significant bits of the double (7 explicit): round at bit 45
+        uint64_t u = (uint64_t)__double_as_longlong(ax);
+        const uint64_t lsb = (u >> 45) & 1u;
+        u += (((uint64_t)1 << 44) - 1) + lsb;
+        u &= ~(((uint64_t)1 << 45) - 1);
+        r = __longlong_as_double((long long)u);
+    }
+    // r is exactly a bf16 magnitude (or >= 2^128 -> overflow to inf)
+    uint32_t fb;
+    if (r >= 0x1.0p128)
+        fb = 0x7f800000u;
+    else
+        fb = __float_as_uint((float)r);
+    return (uint16_t)(sign | (fb >> 16));
+}
+
+
+template <typename TO>
+__device__ __forceinline__ TO narrow(double x);
+template <>
+__device__ __forceinline__ float narrow<float>(double x) {
+    return (float)x;
+}
+template <>
+__device__ __forceinline__ uint16_t narrow<uint16_t>(double x) {
+    return f64_to_bf16_rne(x);
+}
+
+}  // namespace
+
+// One row per workgroup iteration; with aligned rows each thread converts 4
+// consecutive values (two 16-byte loads, one 8- or 16-byte store).
+template <typename TO, bool VEC>
+__global__ void k_convert(const double* __restrict__ A, int64_t lda, int64_t n,
+                          TO* __restrict__ out, int64_t ldo) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const double* a = A + i * lda;
+        TO* o = out + i * ldo;
+        int64_t j0 = 0;
+        if (VEC) {
+            // UN groups of 4 per thread and iteration keep 2 * UN loads in flight
+            constexpr int UN = 4;
+            const int64_t n4 = n / 4 * 4;
+            const int64_t step = 4 * (int64_t)blockDim.x;
+            for (int64_t jb = 4 * (int64_t)threadIdx.x; jb < n4; jb += UN * step) {
+                f64x2 v[UN][2];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const int64_t j = jb + u * step;
+                    if (j < n4) {
+                        const f64x2* src = reinterpret_cast<const f64x2*>(a + j);
+                        v[u][0] = __builtin_nontemporal_load(src);
+                        v[u][1] = __builtin_nontemporal_load(src + 1);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const int64_t j = jb + u * step;
+                    if (j >= n4) continue;
+                    if constexpr (sizeof(TO) == 4) {
+                        const f32x4 w = {narrow<TO>(v[u][0].x), narrow<TO>(v[u][0].y),
+                                         narrow<TO>(v[u][1].x), narrow<TO>(v[u][1].y)};
+                        *reinterpret_cast<f32x4*>(o + j) = w;
+                    } else {
+                        // element j in the low half of the first word (little endian)
+                        const uint32_t lo = (uint32_t)narrow<TO>(v[u][0].x) |
+                                            ((uint32_t)narrow<TO>(v[u][0].y) << 16);
+                        const uint32_t hi = (uint32_t)narrow<TO>(v[u][1].x) |
+                                            ((uint32_t)narrow<TO>(v[u][1].y) << 16);
+                        *reinterpret_cast<uint2*>(o + j) = make_uint2(lo, hi);
+                    }
+                }
+            }
+            j0 = n4;
+        }
+        for (int64_t j = j0 + threadIdx.x; j < n; j += blockDim.x) o[j] = narrow<TO>(a[j]);
+    }
+}
+
+hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
+                          int64_t ldo, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = (int)(n < 16384 ? n : 16384);
+    const size_t eo = to_dtype == 1 ? 4 : 2;
+    const bool vec = (uintptr_t)A % 16 == 0 && lda % 2 == 0 && (uintptr_t)out % (4 * eo) == 0 &&
+                     ldo % 4 == 0;
+    if (to_dtype == 1) {
+        if (vec)
+            hipLaunchKernelGGL((k_convert<float, true>), dim3(blocks), dim3(threads), 0, s, A, lda,
+                               n, (float*)out, ldo);
+        else
+            hipLaunchKernelGGL((k_convert<float, false>), dim3(blocks), dim3(threads), 0, s, A,
+                               lda, n, (float*)out, ldo);
+    } else if (to_dtype == 2) {
+        if (vec)
+            hipLaunchKernelGGL((k_convert<uint16_t, true>), dim3(blocks), dim3(threads), 0, s, A,
+                               lda, n, (uint16_t*)out, ldo);
+        else
+            hipLaunchKernelGGL((k_convert<uint16_t, false>), dim3(blocks), dim3(threads), 0, s, A,
+                               lda, n, (uint16_t*)out, ldo);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace jac

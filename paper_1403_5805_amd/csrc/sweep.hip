@@ -571,45 +571,6 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
     finish_launch<W>(p, dmax, xmax, sq);
 }
 
-// ---------------------------------------------------------------------------
-// FP64 -> FP32 / BF16 conversion of A (round to nearest, ties to even).
-__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x) {
-    if (isnan(x)) return (uint16_t)0x7fc0u;
-    const double ax = fabs(x);
-    const uint32_t sign = (x < 0.0 || (x == 0.0 && signbit(x))) ? 0x8000u : 0u;
-    double r;
-    if (ax < 0x1.0p-126) {
-        // subnormal bf16 range: the quantum is 2^-133
-        r = __builtin_rint(ax * 0x1.0p133) * 0x1.0p-133;
-    } else {
-        // keep 8 significant bits of the double (7 explicit): round at bit 45
-        uint64_t u = (uint64_t)__double_as_longlong(ax);
-        const uint64_t lsb = (u >> 45) & 1u;
-        u += (((uint64_t)1 << 44) - 1) + lsb;
-        u &= ~(((uint64_t)1 << 45) - 1);
-        r = __longlong_as_double((long long)u);
-    }
-    // r is exactly a bf16 magnitude (or >= 2^128 -> overflow to inf)
-    uint32_t fb;
-    if (r >= 0x1.0p128)
-        fb = 0x7f800000u;
-    else
-        fb = __float_as_uint((float)r);
-    return (uint16_t)(sign | (fb >> 16));
-}
-
-__global__ void k_convert_f32(const double* __restrict__ A, int64_t lda, int64_t n,
-                              float* __restrict__ out, int64_t ldo) {
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) out[i * ldo + j] = (float)A[i * lda + j];
-}
-
-__global__ void k_convert_bf16(const double* __restrict__ A, int64_t lda, int64_t n,
-                               uint16_t* __restrict__ out, int64_t ldo) {
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
-            out[i * ldo + j] = f64_to_bf16_rne(A[i * lda + j]);
-}
 
 // alpha_ii of a reduced-precision copy of A, widened to float.
 template <typename TA>
@@ -767,21 +728,6 @@ hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t
     p.chunk = cfg.chunk;
     p.rows_per_wg = cfg.rows_per_wg;
     return launch_kt<double, double, 1>(p, cfg, s);
-}
-
-hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
-                          int64_t ldo, hipStream_t s) {
-    const int threads = 256;
-    const int blocks = (int)(n < 16384 ? n : 16384);
-    if (to_dtype == 1)
-        hipLaunchKernelGGL(k_convert_f32, dim3(blocks), dim3(threads), 0, s, A, lda, n,
-                           (float*)out, ldo);
-    else if (to_dtype == 2)
-        hipLaunchKernelGGL(k_convert_bf16, dim3(blocks), dim3(threads), 0, s, A, lda, n,
-                           (uint16_t*)out, ldo);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
 }
 
 hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64_t n,
