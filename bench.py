@@ -330,7 +330,7 @@ def bench_c3(args):
     res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
     res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                       "kernel": "k_batched<float,KT=32,W=4,TPW=2,U=2>",
+                       "kernel": "k_batched<float,KT=32,W=4,TPW=2,U=1>, two 16-byte loads per lane and block",
                        "mfma_tflops": round(tfs, 2),
                        "mfma_frac_of_157_3": round(tfs / 157.3, 4),
                        "launch_device_ms": round(dev_ms, 3)}

@@ -72,7 +72,7 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     std::vector<size_t> off(count);
     size_t ws = 0;
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
-    auto xld_of = [](int64_t n) { return (n + 31) / 32 * 32; };
+    auto xld_of = [](int64_t n) { return (n + 63) / 64 * 64; };  // a multiple of every block width
     for (int i = 0; i < count; ++i) {
         off[i] = ws;
         ws += 2 * align(sizeof(float) * xld_of(items[i].n) * kt) + align(sizeof(float) * items[i].n);
