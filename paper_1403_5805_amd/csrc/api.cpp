@@ -223,7 +223,12 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
                          hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
                          double* xmax_out, double* kernel_ms, int64_t* launches) {
     int32_t done = 0;
-    int32_t chunk = sync_every > 0 ? sync_every : 4;
+    // Launches queued after the device decided to stop return at once (a few
+    // microseconds each), so a small system, whose sweeps cost about as much
+    // as a launch, starts with a longer group and saves host round trips.
+    const double sweep_bytes =
+        (double)args.n * (double)args.lda * (a_dtype == JACOBI_F64 ? 8 : 4);
+    int32_t chunk = sync_every > 0 ? sync_every : (sweep_bytes <= 64.0 * 1024 * 1024 ? 16 : 4);
     *stop_out = STOP_RUNNING;
     if (profile && (int)c->prof_ev.size() < 2 * 512) {
         while ((int)c->prof_ev.size() < 2 * 512) {
