@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -33,9 +34,10 @@ static double bits_to_double(uint64_t b) {
 
 // Run the persistent MFMA kernel on `count` FP32/BF16 systems (k <= 32).
 // infos[i] receives each system's outcome.
-jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
-                          const jacobi_options& o, int32_t test, double rel, hipStream_t s,
-                          jacobi_info* infos) {
+static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const BatchItem* items,
+                                       int32_t a_dtype, const jacobi_options& o, int32_t test,
+                                       double rel, hipStream_t s, jacobi_info* infos,
+                                       int variant) {
     int kmax = 1;
     int64_t nmax = 1;
     for (int i = 0; i < count; ++i) {
@@ -43,13 +45,6 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         nmax = std::max(nmax, items[i].n);
     }
     const int kt = kmax <= 16 ? 16 : 32;
-    // Kernel shape: many systems (at least one per four CUs) pack better on
-    // the wide shape, a few large ones stream better on the deep one.
-    int variant = count * 4 >= c->num_cus ? 0 : 1;
-    if (const char* env = getenv("JACOBI_BATCHED_SHAPE")) {
-        if (!strcmp(env, "wide")) variant = 0;
-        if (!strcmp(env, "deep")) variant = 1;
-    }
     const int capacity = batched_max_grid(a_dtype, kt, variant, c->num_cus);
     if (capacity < 1) {
         set_error("batched kernel unavailable for this dtype");
@@ -75,7 +70,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     auto xld_of = [](int64_t n) { return (n + 63) / 64 * 64; };  // a multiple of every block width
     for (int i = 0; i < count; ++i) {
         off[i] = ws;
-        ws += 2 * align(sizeof(float) * xld_of(items[i].n) * kt) + align(sizeof(float) * items[i].n);
+        ws += 2 * align(sizeof(float) * xld_of(items[i].n) * kt) +
+              align(sizeof(float) * items[i].n);
     }
     const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
     const size_t job_b = align(sizeof(BJob) * std::max<size_t>(1, plan.jobs.size()));
@@ -156,7 +152,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     ba.max_nwg = plan.max_nwg;
     ba.count = count;
     int rate_khz = 100000;
-    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess ||
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) !=
+            hipSuccess ||
         rate_khz <= 0)
         rate_khz = 100000;
     ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
@@ -200,6 +197,86 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         else
             inf.status = JACOBI_NOT_CONVERGED;
     }
+    return JACOBI_OK;
+}
+
+// Kernel shape for a batch: JACOBI_BATCHED_SHAPE when set; else the shape
+// measured fastest for batches of this class (element type, output width and
+// power-of-two buckets of the system count, largest n and bytes per sweep),
+// found by solving the batch on both shapes the first time the class is seen.
+// Both shapes give bitwise the same results, so the choice only affects
+// speed.  Batches too small to be worth a trial, and batches
+// whose initial approximation aliases the output (a trial would overwrite
+// it), use the rule of thumb: wide for many systems, deep for few.
+jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
+                          const jacobi_options& o, int32_t test, double rel, hipStream_t s,
+                          jacobi_info* infos) {
+    if (const char* env = getenv("JACOBI_BATCHED_SHAPE")) {
+        const int forced = !strcmp(env, "wide") ? 0 : (!strcmp(env, "deep") ? 1 : -1);
+        if (forced >= 0)
+            return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, forced);
+    }
+    int kmax = 1;
+    int64_t nmax = 1;
+    double bytes = 0.0;
+    bool alias = false;
+    for (int i = 0; i < count; ++i) {
+        kmax = std::max<int>(kmax, (int)items[i].k);
+        nmax = std::max(nmax, items[i].n);
+        bytes += (double)items[i].n * (double)items[i].n * (a_dtype == JACOBI_F32 ? 4.0 : 2.0);
+        if (items[i].X0 && items[i].X0 == items[i].X) alias = true;
+    }
+    const int rule = count * 4 >= c->num_cus ? 0 : 1;
+    auto lg = [](double v) {
+        int b = 0;
+        while (v >= 2.0 && b < 62) {
+            v /= 2.0;
+            ++b;
+        }
+        return (uint64_t)b;
+    };
+    const uint64_t key = ((uint64_t)a_dtype << 56) | ((uint64_t)(kmax <= 16 ? 16 : 32) << 48) |
+                         (lg(count) << 32) | (lg((double)nmax) << 16) | lg(bytes);
+    auto hit = c->batched_shape.find(key);
+    if (hit != c->batched_shape.end())
+        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, hit->second);
+    if (alias || bytes < 32.0 * 1024 * 1024 || o.max_iter < 2)
+        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, rule);
+    // Both shapes give the same X and outcomes, so the two timed runs are the
+    // solve itself: the first call of a class costs one extra solve.  An
+    // empty launch of each shape first takes the one-time cost of a kernel's
+    // first launch out of the comparison.
+    {
+        const int kt = kmax <= 16 ? 16 : 32;
+        HIP_TRY(c->warm.ensure(256));
+        int32_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        HIP_TRY(c->stage.ensure(sizeof(zeros)));
+        std::memcpy(c->stage.h, zeros, sizeof(zeros));
+        HIP_TRY(launch_copy16(c->stage.d, c->warm.p, sizeof(zeros), s));
+        BatchArgs wa{};
+        wa.job_off = (const int32_t*)c->warm.p;               // one workgroup, no fixed job
+        wa.queue_head = (uint32_t*)((char*)c->warm.p + 16);
+        wa.queue = (const int32_t*)c->warm.p;
+        wa.queue_len = 0;                                     // and an empty queue
+        for (int v = 0; v < 2; ++v) HIP_TRY(launch_batched(a_dtype, kt, v, wa, 1, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // The other shape runs first: what still favours a later run (caches,
+    // translations) then favours the rule's shape, which stays unless the
+    // other one is faster all the same.
+    const int order[2] = {1 - rule, rule};
+    double ms[2] = {0.0, 0.0};
+    for (int t = 0; t < 2; ++t) {
+        jacobi_status st =
+            run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, order[t]);
+        if (st != JACOBI_OK) return st;
+        ms[t] = count > 0 ? infos[0].device_ms : 0.0;
+    }
+    c->batched_shape[key] = ms[0] < ms[1] ? order[0] : rule;
+    if (std::getenv("JACOBI_BATCHED_TRACE"))
+        std::fprintf(stderr, "jacobi batched shape trial: %s %.3f ms, %s %.3f ms -> %s\n",
+                     order[0] ? "deep" : "wide", ms[0], order[1] ? "deep" : "wide", ms[1],
+                     c->batched_shape[key] ? "deep" : "wide");
     return JACOBI_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -55,6 +56,10 @@ struct jacobi_ctx {
     jac::DevBuf rmeta, xT;
     // staging for descriptor uploads and outcome read-backs
     jac::HostStage stage;
+    // batched kernel shape measured fastest per class of batch; `warm` holds
+    // the empty job table of the warm-up launches
+    std::map<uint64_t, int> batched_shape;
+    jac::DevBuf warm;
 };
 
 namespace jac {

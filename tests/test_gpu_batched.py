@@ -98,6 +98,28 @@ def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
         assert out["wide"][1][i]["status"] == jac.OK
 
 
+def test_shape_tuning_keeps_results(jac, monkeypatch):
+    """The first batch of a class (here 4 x n = 2048, 64 MB per sweep) is timed
+    on both kernel shapes before the real run; the tuned runs (first and
+    cached) give bitwise what each forced shape gives."""
+    import torch
+    sysl = []
+    for idx in range(4):
+        A32, _, B32 = _sys32(2048, 16, 990 + idx)
+        sysl.append((dev(A32), dev(B32)))
+    monkeypatch.delenv("JACOBI_BATCHED_SHAPE", raising=False)
+    say("batched shape tuning")
+    first = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    cached = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    monkeypatch.setenv("JACOBI_BATCHED_SHAPE", "wide")
+    wide = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    monkeypatch.delenv("JACOBI_BATCHED_SHAPE")
+    for i in range(len(sysl)):
+        assert torch.equal(first[0][i], wide[0][i]) and torch.equal(cached[0][i], wide[0][i])
+        assert first[1][i]["iterations"] == wide[1][i]["iterations"] == cached[1][i]["iterations"]
+        assert first[1][i]["status"] == jac.OK
+
+
 def test_failures_isolated(jac):
     """A zero diagonal / NaN right-hand side fails only its own system; its X
     is untouched and its neighbours are bitwise unaffected."""
