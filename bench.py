@@ -230,15 +230,33 @@ def _common(args, metric, value, unit, ms_per_step, dtype, config, higher=True):
             "config": config}
 
 
-def _timed(fn, steps, warmup):
+def _timed(fn, steps, warmup, step_ms=None):
+    """Time exactly `steps` calls after `warmup` untimed ones, bracketed by
+    device synchronisation.  Python's cyclic collector is paused inside the
+    timed region (as timeit does), so a collection of unrelated objects does
+    not land in one step.  Per-step host times go to `step_ms` when given."""
+    import gc
+
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = [fn() for _ in range(steps)]
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, outs
+    outs = []
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            outs.append(fn())
+            if step_ms is not None:
+                step_ms.append(round((time.perf_counter() - t1) * 1e3, 3))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        if gc_was:
+            gc.enable()
+    return el, outs
 
 
 def bench_c1(args):
@@ -304,7 +322,8 @@ def bench_c3(args):
     def step():
         _, infos = jac.solve_batched(systems, outs=outs, ctx=ctx, tol=1e-6, max_iter=1000)
         return infos
-    el, allinfo = _timed(step, args.steps, args.warmup)
+    step_ms = []
+    el, allinfo = _timed(step, args.steps, args.warmup, step_ms)
     infos = allinfo[-1]
     ok = all(i["status"] == jac.OK for i in infos)
     bytes_total = sum(i["iterations"] * (4 * n * n + 3 * 4 * n * 32) for n, i in zip(ns, infos))
@@ -327,6 +346,7 @@ def bench_c3(args):
                           "tol 1e-6, one persistent MFMA launch", "sum_n2": int(sum(n * n for n in ns)),
                           "systems": len(ns)})
     res["all_ok"] = ok
+    res["step_ms"] = step_ms
     res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
     res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,

@@ -31,8 +31,15 @@ def _torch():
     return torch
 
 
+_STATUS_NAMES: dict = {}
+
+
 def status_string(code: int) -> str:
-    return _lib.load().jacobi_status_string(int(code)).decode()
+    code = int(code)
+    name = _STATUS_NAMES.get(code)
+    if name is None:
+        name = _STATUS_NAMES[code] = _lib.load().jacobi_status_string(code).decode()
+    return name
 
 
 def last_error() -> str:
@@ -71,10 +78,17 @@ def _vec_dtype(a_dtype: int, mode: str = "plain"):
     return torch.float64 if (a_dtype == F64 or mode in ("refine", 1)) else torch.float32
 
 
-def _check_operand(t, name: str, device, dtype, shape) -> None:
+def _check_operand(t, name: str, device, dtype, shape) -> int:
     """Reject what would make the library read or write outside a tensor:
     host tensors, another device, another element type or shape, and row
-    views whose rows overlap (row stride below the row length)."""
+    views whose rows overlap (row stride below the row length).  Returns the
+    leading dimension (1 for a vector)."""
+    if t.is_cuda and t.device == device and t.dtype == dtype and t.shape == shape:
+        st = t.stride()
+        if len(st) == 1 and st[0] == 1:
+            return 1
+        if len(st) == 2 and st[1] == 1 and (shape[0] <= 1 or st[0] >= shape[1]):
+            return max(st[0], shape[1])
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
     if t.device != device:
@@ -85,7 +99,7 @@ def _check_operand(t, name: str, device, dtype, shape) -> None:
         raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
     if t.dim() == 2 and t.shape[0] > 1 and t.stride(0) < t.shape[1]:
         raise ValueError(f"{name}: rows overlap (row stride {t.stride(0)} < {t.shape[1]})")
-    _ld(t)
+    return _ld(t)
 
 
 def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype="bf16",
@@ -169,9 +183,8 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
     if x0 is not None:
         _check_operand(x0, "x0", A.device, vdt, B.shape)
     if x0 is not None and not vec and _ld(x0) != _ld(out):
-        x0 = x0.contiguous()
-        if _ld(out) != k:
-            raise ValueError("x0 and out must share a leading dimension")
+        # X0 is read with out's leading dimension
+        x0 = torch.empty((n, _ld(out)), dtype=vdt, device=A.device)[:, :k].copy_(x0)
     o = make_options(**opts)
     info = Info()
     st = lib.jacobi_solve(ctx.handle if ctx else None, n, k, dt, _ptr(A), _ld(A),

@@ -67,7 +67,10 @@ class Info(ctypes.Structure):
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name in _INFO_KEYS}
+
+
+_INFO_KEYS = tuple(name for name, _ in Info._fields_ if name != "reserved")
 
 
 class System(ctypes.Structure):

@@ -26,40 +26,41 @@ def solve_batched(systems, *, outs=None, ctx=None, stream=None, tol=1e-8, max_it
     arr = (_lib.System * count)()
     xs = []
     keep = []
+    dev = systems[0][0].device
+    adt = systems[0][0].dtype
+    vdt = _vec_dtype(dt)
     for i, sysd in enumerate(systems):
         A, B = sysd[0], sysd[1]
         x0 = sysd[2] if len(sysd) > 2 else None
-        if _a_dtype(A) != dt:
+        if A.dtype != adt:
             raise TypeError("all systems of a batch share A's dtype")
-        vec = B.dim() == 1
+        bshape = B.shape
+        vec = len(bshape) == 1
         n = A.shape[0]
-        k = 1 if vec else B.shape[1]
-        dev = systems[0][0].device
-        vdt = _vec_dtype(dt)
-        if A.dim() != 2 or A.shape[0] != A.shape[1] or B.dim() > 2 or B.shape[0] != n:
+        k = 1 if vec else bshape[1]
+        if A.dim() != 2 or A.shape[1] != n or len(bshape) > 2 or bshape[0] != n:
             raise ValueError(f"system {i}: A must be (n, n) and B (n,) or (n, k)")
-        _check_operand(A, f"A[{i}]", dev, A.dtype, (n, n))
-        _check_operand(B, f"B[{i}]", dev, vdt, B.shape)
+        S = arr[i]
+        S.lda = _check_operand(A, f"A[{i}]", dev, adt, (n, n))
+        ldb = _check_operand(B, f"B[{i}]", dev, vdt, bshape)
         X = outs[i] if outs is not None else torch.empty_like(B)
-        _check_operand(X, f"out[{i}]", dev, vdt, B.shape)
+        ldx = _check_operand(X, f"out[{i}]", dev, vdt, bshape)
         if x0 is not None:
-            _check_operand(x0, f"x0[{i}]", dev, vdt, B.shape)
-            if _ld(x0) != _ld(X):
-                x0 = x0.contiguous()
+            if _check_operand(x0, f"x0[{i}]", dev, vdt, bshape) != ldx:
+                # X0 is read with X's leading dimension
+                x0 = torch.empty((n, ldx), dtype=vdt, device=dev)[:, :k].copy_(x0)
+            S.X0 = x0.data_ptr()
         keep.append(x0)
-        arr[i].n = n
-        arr[i].k = k
-        arr[i].A = A.data_ptr()
-        arr[i].lda = _ld(A)
-        arr[i].B = B.data_ptr()
-        arr[i].ldb = 1 if vec else _ld(B)
-        arr[i].X0 = x0.data_ptr() if x0 is not None else None
-        arr[i].X = X.data_ptr()
-        arr[i].ldx = 1 if vec else _ld(X)
+        S.n = n
+        S.k = k
+        S.A = A.data_ptr()
+        S.B = B.data_ptr()
+        S.ldb = ldb
+        S.X = X.data_ptr()
+        S.ldx = ldx
         xs.append(X)
     o = make_options(tol=tol, max_iter=max_iter, norm=norm)
     infos = (_lib.Info * count)()
-    dev = systems[0][0].device
     st = lib.jacobi_solve_batched(ctx.handle if ctx else None, count, arr, dt, ctypes.byref(o),
                                   _stream_handle(stream, dev), infos)
     if st != 0:

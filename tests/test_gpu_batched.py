@@ -204,3 +204,34 @@ def test_c3_full_size_properties(jac):
         xo, io = _oracle32(A32, B32, 1e-6, 1000)
         assert abs(infos[i]["iterations"] - io["iterations"]) <= 1
         assert rel_err(host(xs[i]), xo) <= REL_F32
+
+
+def test_strided_out_with_x0(jac):
+    """An output view with a padded row stride and a dense x0: X0 is read with
+    the output's leading dimension, so the binding relays x0 in that layout;
+    the results equal those of dense outputs bitwise."""
+    import torch
+    shapes = [(300, 5), (77, 16)]
+    sysl, sysl_pad, pads = [], [], []
+    for idx, (n, k) in enumerate(shapes):
+        A32, _, B32 = _sys32(n, k, 900 + idx)
+        x0 = np.random.default_rng(idx).uniform(-1, 1, size=(n, k)).astype(np.float32)
+        sysl.append((dev(A32), dev(B32), dev(x0)))
+        pad = torch.full((n, k + 3), 7.0, dtype=torch.float32, device="cuda")
+        pads.append(pad)
+        sysl_pad.append((dev(A32), dev(B32), dev(x0)))
+    say("strided out with x0")
+    xs, infos = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+    xp, infp = jac.solve_batched(sysl_pad, outs=[p[:, :k] for p, (_, k) in zip(pads, shapes)],
+                                 tol=1e-6, max_iter=200)
+    for (n, k), X, Y, P, a, b in zip(shapes, xs, xp, pads, infos, infp):
+        assert a["status"] == jac.OK and a["iterations"] == b["iterations"], (n, k, a, b)
+        assert torch.equal(X, Y), (n, k)
+        assert bool((P[:, k:] == 7.0).all()), "padding columns written"
+    # the single-system entry point relays x0 the same way
+    n, k = shapes[0]
+    A, B, x0 = sysl[0]
+    Y, info = jac.solve(A, B, x0, out=pads[0][:, :k], tol=1e-6, max_iter=200)
+    assert info["status"] == jac.OK
+    X, _ = jac.solve(A, B, x0, tol=1e-6, max_iter=200)
+    assert torch.equal(X, Y)
