@@ -155,6 +155,228 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// One sweep over rows [r0, r1) of system S: x_new = (b - (A - D) x_old) / a_ii
+// for every column of those rows, read from `xin` and written to `xout` (both
+// transposed), with this thread's share of the distance statistics added to
+// dmax, xmax (double bits of max |x_new - x_old| and max |x_new|) and sq (sum
+// of squares).  Every thread of the workgroup calls it; `red` is the LDS tile
+// of the wave-order reduction.  A row's value depends only on the row, its
+// system and W, not on [r0, r1): the same X comes out of any row split.
+template <typename TA, int KT, int W, int TPW, int U>
+__device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1,
+                                           const float* xin, float* xout, float* red, int tid,
+                                           int wave, uint64_t& dmax, uint64_t& xmax, double& sq) {
+    constexpr int LPL = 2;                     // 16-byte loads per lane and block
+    constexpr int V16 = 16 / (int)sizeof(TA);  // A values per 16-byte load
+    constexpr int VEC = LPL * V16;             // A values per lane and block
+    constexpr int BW = 4 * VEC;                // columns of one A block (32 or 64)
+    constexpr int NT = KT / 16;                // 16-column output tiles
+    constexpr int NS = VEC / 4;                // 4-step MFMA groups per block
+    const int lane = tid & 63, grp = lane >> 4, li = lane & 15;
+    const TA* A = reinterpret_cast<const TA*>(S.A);
+    const int64_t n = S.n;
+    const int64_t xld = S.xld;
+    const int k = S.k;
+    const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
+    const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks loadable with 16-byte loads
+    // this wave's vector-loadable blocks: b = wave + W * t, t < ntw
+    const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
+    const int64_t nfull = (ntw / U) * U;
+    gptr<float> xrow[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
+    // Row pointers of the pass starting at row pr.  Rows past the job
+    // (a short last pass) re-read the job's last row, which the cache
+    // serves, and are discarded.
+    auto rows_of = [&](gptr<TA> (&rows)[TPW], int64_t pr) {
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            int64_t ri = pr + 16 * q + li;
+            if (ri >= r1) ri = r1 - 1;
+            rows[q] = gbl(A + ri * S.lda + VEC * grp);
+        }
+    };
+    auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg)
+                bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
+    };
+    // Loads of U blocks starting at this wave's block t0.
+    auto issue = [&](const gptr<TA> (&rows)[TPW], u32x4 (&v)[U][TPW][LPL],
+                     f32x4 (&bx)[U][NT][NS], int64_t t0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t b = wave + W * (t0 + u);
+#pragma unroll
+            for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                for (int j = 0; j < LPL; ++j)
+                    v[u][q][j] = __builtin_nontemporal_load(
+                        (gptr<u32x4>)(rows[q] + b * BW + j * V16));
+            load_b(bx[u], b);
+        }
+    };
+    // First pipeline stage of the next pass, loaded while the current
+    // pass finishes its reduction and epilogue.
+    u32x4 v0[U][TPW][LPL];
+    f32x4 b0[U][NT][NS];
+    bool preloaded = false;
+    gptr<TA> arow[TPW];
+    rows_of(arow, r0);
+    for (int64_t pr = r0; pr < r1; pr += 16 * TPW) {
+        int64_t rt[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) rt[q] = pr + 16 * q;
+        f32x4 acc[TPW][NT];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[q][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+        // MFMAs of one A block (the TPW tiles share the B operand).
+        auto mfma_block = [&](float (&a)[TPW][VEC], const f32x4 (&bx)[NT][NS], int64_t b) {
+            // Tile q's diagonal lies in block rt[q] / BW (BW is 32 or
+            // 64, tiles start at multiples of 16): only that block,
+            // a wave-uniform test, masks the lane's element dpos.
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                if (b == rt[q] / BW) {
+                    const int dpos = (int)(rt[q] - b * BW) + li - VEC * grp;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
+                }
+            }
+            // Consecutive MFMAs update different accumulators.
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a[q][4 * sg + r], bx[t][sg][r], acc[q][t], 0, 0, 0);
+        };
+        // Vector-loadable blocks: two pipeline stages of U blocks; the
+        // loads of one stage are in flight during the MFMAs of the other.
+        if (nfull > 0) {
+            u32x4 v1[U][TPW][LPL];
+            f32x4 b1[U][NT][NS];
+            auto consume = [&](u32x4 (&v)[U][TPW][LPL], f32x4 (&bx)[U][NT][NS],
+                               int64_t t0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    float a[TPW][VEC];
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                        for (int j = 0; j < LPL; ++j) unpack<TA>(v[u][q][j], a[q] + j * V16);
+                    mfma_block(a, bx[u], wave + W * (t0 + u));
+                }
+            };
+            // The scheduling barriers keep the compiler from sinking
+            // the loads below the MFMAs that should hide them.
+            if (!preloaded) issue(arow, v0, b0, 0);
+            int64_t t = 0;
+            for (; t + 3 * U <= nfull; t += 2 * U) {
+                issue(arow, v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v0, b0, t);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(arow, v0, b0, t + 2 * U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (t + 2 * U <= nfull) {
+                issue(arow, v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v0, b0, t);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v1, b1, t + U);
+            } else {
+                consume(v0, b0, t);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // Start the next pass's first stage now (A and the iterate do
+        // not change within a sweep).
+        gptr<TA> arow_next[TPW];
+        const bool more = pr + 16 * TPW < r1;
+        if (more) rows_of(arow_next, pr + 16 * TPW);
+        preloaded = more && nfull > 0;
+        if (preloaded) issue(arow_next, v0, b0, 0);
+        // Remaining blocks of this wave (ragged tail, or every block of
+        // rows that are not 16-byte aligned).
+        for (int64_t b = wave + W * nfull; b < nb; b += W) {
+            float a[TPW][VEC];
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                if (b < nbf) {
+#pragma unroll
+                    for (int j = 0; j < LPL; ++j) {
+                        const u32x4 v = __builtin_nontemporal_load(
+                            (gptr<u32x4>)(arow[q] + b * BW + j * V16));
+                        unpack<TA>(v, a[q] + j * V16);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int64_t col = b * BW + VEC * grp + e;
+                        a[q][e] = col < n ? widen1<TA>(arow[q][b * BW + e]) : 0.0f;
+                    }
+                }
+            }
+            f32x4 bx[NT][NS];
+            load_b(bx, b);  // zero padded past n
+            mfma_block(a, bx, b);
+        }
+        // Add the W partial tiles in wave order.  Tile element (i, j)
+        // sits in lane 16 * (i / 4) + j, register i % 4.
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[(((wave * TPW + q) * NT + t) * 4 + v) * 64 + lane] = acc[q][t][v];
+        __syncthreads();
+        // Epilogue: thread e takes column cc of tile (q, t), row ri, so
+        // consecutive threads write consecutive rows of the transposed
+        // iterate.
+        for (int e = tid; e < TPW * NT * 256; e += W * 64) {
+            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+            const int q = qt / NT, t = qt - q * NT;
+            const int l = 16 * (ri >> 2) + cc, v = ri & 3;
+            float s = 0.0f;
+#pragma unroll
+            for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
+            const int64_t i = pr + 16 * q + ri;
+            const int c = t * 16 + cc;
+            if (i < r1 && c < k) {
+                const float xo = *gbl(xin + (int64_t)c * xld + i);
+                const float xn = (*gbl(S.B + i * S.ldb + c) - s) / *gbl(S.diag + i);
+                *gout(xout + (int64_t)c * xld + i) = xn;
+                const double dd = fabs((double)xn - (double)xo);
+                const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                dmax = db > dmax ? db : dmax;
+                xmax = mb > xmax ? mb : xmax;
+                sq += dd * dd;
+            }
+        }
+        __syncthreads();  // red is reused by the next pass
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) arow[q] = arow_next[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The persistent kernel.
 //   W   waves per workgroup (they split the columns of every tile)
 //   TPW 16-row tiles per pass (they share every B operand load)
@@ -162,12 +384,7 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 //   MINB workgroups per CU the register budget is sized for
 template <typename TA, int KT, int W, int TPW, int U, int MINB>
 __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
-    constexpr int LPL = 2;                     // 16-byte loads per lane and block
-    constexpr int V16 = 16 / (int)sizeof(TA);  // A values per 16-byte load
-    constexpr int VEC = LPL * V16;             // A values per lane and block
-    constexpr int BW = 4 * VEC;                // columns of one A block (32 or 64)
     constexpr int NT = KT / 16;                // 16-column output tiles
-    constexpr int NS = VEC / 4;                // 4-step MFMA groups per block
     __shared__ float red[W * TPW * NT * 256];
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
@@ -176,7 +393,6 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block tests stay scalar
-    const int grp = lane >> 4, li = lane & 15;
 
     __shared__ int32_t s_next;
     int jb = p.job_off[blockIdx.x];
@@ -209,16 +425,9 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
             __hip_atomic_load(&st->bad_rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
                 INT64_MAX)
             continue;  // invalid input: no sweep runs, X untouched
-        const TA* A = reinterpret_cast<const TA*>(S.A);
-        const int64_t n = S.n;
         const int64_t xld = S.xld;
         const int k = S.k;
         const bool split = S.nwg > 1;
-        const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
-        const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks loadable with 16-byte loads
-        // this wave's vector-loadable blocks: b = wave + W * t, t < ntw
-        const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
-        const int64_t nfull = (ntw / U) * U;
         const float* xfinal = S.buf0;
         int32_t final_k = 0;
         uint32_t final_stop = STOP_RUNNING;
@@ -230,198 +439,8 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
             float* xout = (sweep & 1) ? S.buf1 : S.buf0;
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            gptr<float> xrow[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
-            // Row pointers of the pass starting at row pr.  Rows past the job
-            // (a short last pass) re-read the job's last row, which the cache
-            // serves, and are discarded.
-            auto rows_of = [&](gptr<TA> (&rows)[TPW], int64_t pr) {
-#pragma unroll
-                for (int q = 0; q < TPW; ++q) {
-                    int64_t ri = pr + 16 * q + li;
-                    if (ri >= job.r1) ri = job.r1 - 1;
-                    rows[q] = gbl(A + ri * S.lda + VEC * grp);
-                }
-            };
-            auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int sg = 0; sg < NS; ++sg)
-                        bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
-            };
-            // Loads of U blocks starting at this wave's block t0.
-            auto issue = [&](const gptr<TA> (&rows)[TPW], u32x4 (&v)[U][TPW][LPL],
-                             f32x4 (&bx)[U][NT][NS], int64_t t0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t b = wave + W * (t0 + u);
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                        for (int j = 0; j < LPL; ++j)
-                            v[u][q][j] = __builtin_nontemporal_load(
-                                (gptr<u32x4>)(rows[q] + b * BW + j * V16));
-                    load_b(bx[u], b);
-                }
-            };
-            // First pipeline stage of the next pass, loaded while the current
-            // pass finishes its reduction and epilogue.
-            u32x4 v0[U][TPW][LPL];
-            f32x4 b0[U][NT][NS];
-            bool preloaded = false;
-            gptr<TA> arow[TPW];
-            rows_of(arow, job.r0);
-            for (int64_t pr = job.r0; pr < job.r1; pr += 16 * TPW) {
-                int64_t rt[TPW];
-#pragma unroll
-                for (int q = 0; q < TPW; ++q) rt[q] = pr + 16 * q;
-                f32x4 acc[TPW][NT];
-#pragma unroll
-                for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) acc[q][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
-                // MFMAs of one A block (the TPW tiles share the B operand).
-                auto mfma_block = [&](float (&a)[TPW][VEC], const f32x4 (&bx)[NT][NS], int64_t b) {
-                    // Tile q's diagonal lies in block rt[q] / BW (BW is 32 or
-                    // 64, tiles start at multiples of 16): only that block,
-                    // a wave-uniform test, masks the lane's element dpos.
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q) {
-                        if (b == rt[q] / BW) {
-                            const int dpos = (int)(rt[q] - b * BW) + li - VEC * grp;
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
-                        }
-                    }
-                    // Consecutive MFMAs update different accumulators.
-#pragma unroll
-                    for (int sg = 0; sg < NS; ++sg)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-#pragma unroll
-                            for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                                for (int t = 0; t < NT; ++t)
-                                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                        a[q][4 * sg + r], bx[t][sg][r], acc[q][t], 0, 0, 0);
-                };
-                // Vector-loadable blocks: two pipeline stages of U blocks; the
-                // loads of one stage are in flight during the MFMAs of the other.
-                if (nfull > 0) {
-                    u32x4 v1[U][TPW][LPL];
-                    f32x4 b1[U][NT][NS];
-                    auto consume = [&](u32x4 (&v)[U][TPW][LPL], f32x4 (&bx)[U][NT][NS],
-                                       int64_t t0) {
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            float a[TPW][VEC];
-#pragma unroll
-                            for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                                for (int j = 0; j < LPL; ++j) unpack<TA>(v[u][q][j], a[q] + j * V16);
-                            mfma_block(a, bx[u], wave + W * (t0 + u));
-                        }
-                    };
-                    // The scheduling barriers keep the compiler from sinking
-                    // the loads below the MFMAs that should hide them.
-                    if (!preloaded) issue(arow, v0, b0, 0);
-                    int64_t t = 0;
-                    for (; t + 3 * U <= nfull; t += 2 * U) {
-                        issue(arow, v1, b1, t + U);
-                        __builtin_amdgcn_sched_barrier(0);
-                        consume(v0, b0, t);
-                        __builtin_amdgcn_sched_barrier(0);
-                        issue(arow, v0, b0, t + 2 * U);
-                        __builtin_amdgcn_sched_barrier(0);
-                        consume(v1, b1, t + U);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    if (t + 2 * U <= nfull) {
-                        issue(arow, v1, b1, t + U);
-                        __builtin_amdgcn_sched_barrier(0);
-                        consume(v0, b0, t);
-                        __builtin_amdgcn_sched_barrier(0);
-                        consume(v1, b1, t + U);
-                    } else {
-                        consume(v0, b0, t);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                // Start the next pass's first stage now (A and the iterate do
-                // not change within a sweep).
-                gptr<TA> arow_next[TPW];
-                const bool more = pr + 16 * TPW < job.r1;
-                if (more) rows_of(arow_next, pr + 16 * TPW);
-                preloaded = more && nfull > 0;
-                if (preloaded) issue(arow_next, v0, b0, 0);
-                // Remaining blocks of this wave (ragged tail, or every block of
-                // rows that are not 16-byte aligned).
-                for (int64_t b = wave + W * nfull; b < nb; b += W) {
-                    float a[TPW][VEC];
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q) {
-                        if (b < nbf) {
-#pragma unroll
-                            for (int j = 0; j < LPL; ++j) {
-                                const u32x4 v = __builtin_nontemporal_load(
-                                    (gptr<u32x4>)(arow[q] + b * BW + j * V16));
-                                unpack<TA>(v, a[q] + j * V16);
-                            }
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) {
-                                const int64_t col = b * BW + VEC * grp + e;
-                                a[q][e] = col < n ? widen1<TA>(arow[q][b * BW + e]) : 0.0f;
-                            }
-                        }
-                    }
-                    f32x4 bx[NT][NS];
-                    load_b(bx, b);  // zero padded past n
-                    mfma_block(a, bx, b);
-                }
-                // Add the W partial tiles in wave order.  Tile element (i, j)
-                // sits in lane 16 * (i / 4) + j, register i % 4.
-#pragma unroll
-                for (int q = 0; q < TPW; ++q)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            red[(((wave * TPW + q) * NT + t) * 4 + v) * 64 + lane] = acc[q][t][v];
-                __syncthreads();
-                // Epilogue: thread e takes column cc of tile (q, t), row ri, so
-                // consecutive threads write consecutive rows of the transposed
-                // iterate.
-                for (int e = tid; e < TPW * NT * 256; e += W * 64) {
-                    const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
-                    const int q = qt / NT, t = qt - q * NT;
-                    const int l = 16 * (ri >> 2) + cc, v = ri & 3;
-                    float s = 0.0f;
-#pragma unroll
-                    for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
-                    const int64_t i = pr + 16 * q + ri;
-                    const int c = t * 16 + cc;
-                    if (i < job.r1 && c < k) {
-                        const float xo = *gbl(xin + (int64_t)c * xld + i);
-                        const float xn = (*gbl(S.B + i * S.ldb + c) - s) / *gbl(S.diag + i);
-                        *gout(xout + (int64_t)c * xld + i) = xn;
-                        const double dd = fabs((double)xn - (double)xo);
-                        const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
-                        dmax = db > dmax ? db : dmax;
-                        xmax = mb > xmax ? mb : xmax;
-                        sq += dd * dd;
-                    }
-                }
-                __syncthreads();  // red is reused by the next pass
-                if (more) {
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q) arow[q] = arow_next[q];
-                }
-            }
+            sweep_rows<TA, KT, W, TPW, U>(S, job.r0, job.r1, xin, xout, red, tid, wave, dmax,
+                                          xmax, sq);
             // ---- workgroup reduction of the distance statistics
             dmax = wmax(dmax);
             xmax = wmax(xmax);
@@ -531,6 +550,191 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// The lockstep schedule.  Round r is sweep r of every system still running:
+// the rows of all systems are cut into work items (largest systems first) and
+// every workgroup takes the next item from one atomic ticket counter until
+// the round's items are gone, then waits at one grid barrier.  No workgroup
+// ever waits for one system: a few large systems and many small ones load the
+// chip evenly.  Each item adds its distance maxima to its system's slot (and
+// its sum of squares to its own slot for the Euclidean norm); the item that
+// completes a system's round, found by a per-system ticket, applies the stop
+// test.  A system that stops after sweep r is copied to the caller's X by its
+// items in round r + 1.  The loop ends one round after the last system stops.
+template <typename TA, int KT, int W, int TPW, int U, int MINB>
+__global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
+    constexpr int NT = KT / 16;
+    __shared__ float red[W * TPW * NT * 256];
+    __shared__ uint64_t red_d[W], red_m[W];
+    __shared__ double red_s[W];
+    __shared__ int32_t s_item, s_done;
+    __shared__ bool s_bad;
+    __shared__ uint32_t s_active, s_abort;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint64_t per_round = (uint64_t)p.nitems + gridDim.x;  // tickets taken per round
+    bool last = p.active0 == 0;  // a round that only copies results out
+    for (int r = 1;; ++r) {
+        const uint64_t base = (uint64_t)(r - 1) * per_round;
+        for (;;) {
+            __syncthreads();  // s_item and red are reused
+            if (tid == 0) {
+                // One thread reads the item's state for the whole workgroup:
+                // `done` of this item's system changes only after its last
+                // item of the round, so it is fixed while this item runs.
+                const uint64_t h = __hip_atomic_fetch_add(&p.ctl->head, (uint64_t)1,
+                                                          __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                const int32_t it = h - base < (uint64_t)p.nitems ? (int32_t)(h - base) : -1;
+                s_item = it;
+                if (it >= 0) {
+                    BState* st = &p.st[p.items[it].sys];
+                    s_done = __hip_atomic_load(&st->done, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    s_bad = __hip_atomic_load(&st->bad_diag, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX ||
+                            __hip_atomic_load(&st->bad_rhs, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX;
+                }
+            }
+            __syncthreads();
+            const int32_t it = s_item;
+            if (it < 0) break;
+            const BJob item = p.items[it];
+            BState* st = &p.st[item.sys];
+            const int32_t done = s_done;
+            const bool bad = s_bad;
+            if (done == r) {
+                // stopped after sweep r - 1: this item's rows of the final iterate
+                if (bad) continue;
+                const BSys S = p.sys[item.sys];
+                const float* xsrc = ((r - 1) & 1) ? S.buf1 : S.buf0;
+                const int k = S.k;
+                for (int64_t e = tid; e < (int64_t)(item.r1 - item.r0) * k; e += W * 64) {
+                    const int64_t i = item.r0 + e / k;
+                    const int c = (int)(e % k);
+                    S.X[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
+                }
+                continue;
+            }
+            if (done != 0 || last) continue;
+            const BSys S = p.sys[item.sys];
+            uint64_t dmax = 0, xmax = 0;
+            double sq = 0.0;
+            if (!bad) {
+                const float* xin = (r & 1) ? S.buf0 : S.buf1;
+                float* xout = (r & 1) ? S.buf1 : S.buf0;
+                sweep_rows<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
+                                              dmax, xmax, sq);
+            }
+            dmax = wmax(dmax);
+            xmax = wmax(xmax);
+            sq = wsum(sq);
+            if (lane == 0) {
+                red_d[wave] = dmax;
+                red_m[wave] = xmax;
+                red_s[wave] = sq;
+            }
+            __syncthreads();  // every wave's x_new stores precede tid 0's release below
+            if (tid == 0) {
+                uint64_t D = 0, M = 0;
+                double Q = 0.0;
+                for (int w = 0; w < W; ++w) {
+                    D = red_d[w] > D ? red_d[w] : D;
+                    M = red_m[w] > M ? red_m[w] : M;
+                    Q += red_s[w];
+                }
+                if (!bad) {
+                    if (S.norm == 1)
+                        __hip_atomic_store(&p.item_parts[it], Q, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(&st->dmax[0], D, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(&st->xmax[0], M, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+                const uint32_t t = __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (t + 1 == (uint32_t)(S.it1 - S.it0)) {
+                    // the last item of this system's round: the stop test
+                    if (bad) {
+                        __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        D = __hip_atomic_load(&st->dmax[0], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        M = __hip_atomic_load(&st->xmax[0], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (S.norm == 1) {
+                            Q = 0.0;  // item order: independent of the schedule
+                            for (int j = S.it0; j < S.it1; ++j)
+                                Q += __hip_atomic_load(&p.item_parts[j], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        const double delta = (S.norm == 1) ? sqrt(Q) : bitsd(D);
+                        uint32_t flag = STOP_RUNNING;
+                        if (!isfinite(delta))
+                            flag = STOP_DIVERGED;
+                        else if (S.test == TEST_ABS ? (delta < S.tol)
+                                                    : (delta <= S.rel * bitsd(M)))
+                            flag = STOP_CONVERGED;
+                        __hip_atomic_store(&st->dmax[0], (uint64_t)0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->xmax[0], (uint64_t)0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        if (flag != STOP_RUNNING || r == S.max_iter) {
+                            __hip_atomic_store(&st->status, flag, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&st->iterations, r, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&st->final_delta, dbits(delta), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&st->done, r + 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+        }
+        if (last) break;
+        // ---- grid barrier: one release (the arrival) and one acquire per round
+        if (tid == 0) {
+            __hip_atomic_fetch_add(&p.ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = gridDim.x * (uint32_t)r;
+            const uint64_t t0 = wall_clock64();
+            uint32_t abort = 0;
+            while (__hip_atomic_load(&p.ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (__hip_atomic_load(&p.ctl->abort, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    (int64_t)(wall_clock64() - t0) > p.spin_limit) {
+                    __hip_atomic_store(&p.ctl->abort, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    abort = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_abort = abort;
+            s_active = __hip_atomic_load(&p.ctl->active, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (s_abort) break;
+        // Every running system stops by its own max_iter, so the second test
+        // never decides alone; it bounds the loop whatever the counters say.
+        if (s_active == 0 || r >= p.max_rounds) last = true;
+    }
+}
+
+// ---------------------------------------------------------------------------
 constexpr int kBW = 4;   // waves per workgroup
 constexpr int kBU = 1;   // A blocks per pipeline stage (each block is two loads per row)
 
@@ -588,6 +792,39 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
         hipLaunchKernelGGL((k_batched_setup<bf16_t>), dim3((unsigned)bx, count), dim3(256), 0, s,
                            sys, st, kt);
     return hipGetLastError();
+}
+
+template <typename TA, int KT>
+static const void* rounds_fn(int variant) {
+    if (variant == 1) return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 1), kBU, 1>;
+    return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2>;
+}
+
+static const void* pick_rounds(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 1)
+        return kt <= 16 ? rounds_fn<float, 16>(variant) : rounds_fn<float, 32>(variant);
+    if (a_dtype == 2)
+        return kt <= 16 ? rounds_fn<bf16_t, 16>(variant) : rounds_fn<bf16_t, 32>(variant);
+    return nullptr;
+}
+
+int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus) {
+    const void* fn = pick_rounds(a_dtype, kt, variant);
+    if (!fn) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * num_cus;
+}
+
+hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
+                         hipStream_t s) {
+    const void* fn = pick_rounds(a_dtype, kt, variant);
+    if (!fn) return hipErrorInvalidValue;
+    BatchArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBW * 64), args, 0u, s);
 }
 
 hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,

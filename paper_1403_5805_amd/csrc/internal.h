@@ -138,6 +138,7 @@ struct BSys {
     double rel;        // TEST_REL factor
     int32_t norm;      // 0 inf, 1 l2
     int32_t aligned;   // rows of A 16-byte aligned
+    int32_t it0, it1;  // lockstep schedule: the system's work items [it0, it1)
 };
 
 // Per-system control state (device), zeroed before the launch.
@@ -151,6 +152,17 @@ struct alignas(64) BState {
     uint64_t final_delta;    // double bits
     int64_t bad_diag;        // validation: min over bad diagonals of 2*row + (non-finite ? 1 : 0)
     int64_t bad_rhs;         // validation: first row with a non-finite B or X0 entry
+    int32_t done;            // lockstep schedule: 0 running, r + 1 stopped after sweep r
+                             // (its X is copied out in round r + 1), -1 invalid input
+};
+
+// Grid-wide control words of the lockstep schedule (device), zeroed before
+// the launch except `active`.
+struct alignas(64) BCtl {
+    uint64_t head;    // work-item tickets handed out (all rounds)
+    uint32_t bar;     // grid barrier arrivals (all rounds)
+    uint32_t active;  // systems still sweeping
+    uint32_t abort;   // 1: a barrier wait timed out
 };
 
 struct BatchArgs {
@@ -165,12 +177,25 @@ struct BatchArgs {
     int32_t max_nwg;
     int32_t count;
     int64_t spin_limit;       // wall-clock ticks (100 MHz) before a barrier wait gives up
+    // lockstep schedule (k_rounds): one grid barrier per sweep, rows dealt
+    // out as work items
+    const BJob* items;        // rows [r0, r1) of system sys; `rank` unused
+    double* item_parts;       // [nitems] L2 partial sums of the current sweep
+    BCtl* ctl;
+    int32_t nitems;
+    int32_t active0;          // systems with max_iter > 0
+    int32_t max_rounds;       // largest max_iter among them: no round runs past it
 };
 
 hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,
                                 int32_t count, int64_t max_n, hipStream_t s);
 hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
                           hipStream_t s);
+// The lockstep schedule: every workgroup sweeps work items of any system, all
+// systems advance one sweep per round, one grid barrier per round.
+hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
+                         hipStream_t s);
+int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 int batched_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 
 // ---------------------------------------------------------------------------

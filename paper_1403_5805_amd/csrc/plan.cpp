@@ -105,4 +105,35 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
     return p;
 }
 
+// About eight items per workgroup and round keeps the round's tail short (the
+// last items are the small systems'); the floor keeps the per-item ticket and
+// pipeline start small next to the item's loads.
+ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes) {
+    ItemPlan p;
+    const int count = (int)n.size();
+    p.it0.assign(count, 0);
+    p.it1.assign(count, 0);
+    double total = 0.0;
+    for (int64_t v : n) total += (double)v * (double)v * elem_bytes;
+    const double target =
+        std::min(2.0 * 1024 * 1024,
+                 std::max(128.0 * 1024, total / (8.0 * std::max(1, capacity))));
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    const int64_t unit = 16 * (int64_t)tpp;
+    for (int s : order) {
+        p.it0[s] = (int32_t)p.items.size();
+        if (n[s] > 0) {
+            int64_t rows = (int64_t)std::ceil(target / ((double)n[s] * elem_bytes));
+            rows = std::max<int64_t>(unit, (rows + unit - 1) / unit * unit);
+            for (int64_t r0 = 0; r0 < n[s]; r0 += rows)
+                p.items.push_back(BJob{s, 0, (int32_t)r0, (int32_t)std::min(n[s], r0 + rows)});
+        }
+        p.it1[s] = (int32_t)p.items.size();
+    }
+    p.grid = std::min<int64_t>(std::max(1, capacity), (int64_t)p.items.size());
+    return p;
+}
+
 }  // namespace jac

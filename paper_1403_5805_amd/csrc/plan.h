@@ -39,4 +39,21 @@ struct Plan {
 Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll, int bw,
                int max_split = 1 << 30);
 
+// Work items of the lockstep schedule: the rows of every system cut into
+// chunks (systems by decreasing n, rows in order); items of system s are
+// items[it0[s] .. it1[s]).
+struct ItemPlan {
+    std::vector<BJob> items;  // rank = 0
+    std::vector<int32_t> it0, it1;
+    int grid = 0;             // workgroups to launch: min(capacity, items)
+};
+
+// Guarantees: every system with n[s] >= 1 has at least one item; its items
+// cover rows [0, n[s]) exactly once, in order, each a multiple of 16 * tpp
+// rows long except the system's last; an item holds about
+// clamp(total bytes / (capacity * 8), 128 KiB, 2 MiB) of A (elem_bytes per
+// value) or the whole system when that is smaller.  Systems with n[s] = 0
+// get an empty range.
+ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes);
+
 }  // namespace jac

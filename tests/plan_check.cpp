@@ -2,15 +2,40 @@
 // Reads "capacity tpp unroll bw count n_0 ... n_{count-1}" from stdin and
 // prints the plan: "grid G", one "nwg i v" line per system, one
 // "wg g sys rank r0 r1" line per fixed job and one "q sys" line per queue
-// entry, in queue order.  Built with g++; no GPU involved.
+// entry, in queue order.  With "items capacity tpp elem_bytes count n_0 ..."
+// it prints the lockstep work items instead: "grid G", one "range s it0 it1"
+// line per system and one "item j sys r0 r1" line per item.  Built with g++;
+// no GPU involved.
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "../paper_1403_5805_amd/csrc/plan.h"
 
+static int items_mode() {
+    int capacity, tpp, elem, count;
+    if (std::scanf("%d %d %d %d", &capacity, &tpp, &elem, &count) != 4) return 2;
+    std::vector<int64_t> n(count);
+    for (int i = 0; i < count; ++i) {
+        long long v;
+        if (std::scanf("%lld", &v) != 1) return 2;
+        n[i] = v;
+    }
+    const jac::ItemPlan p = jac::make_items(n, capacity, tpp, elem);
+    std::printf("grid %d\n", p.grid);
+    for (int i = 0; i < count; ++i) std::printf("range %d %d %d\n", i, p.it0[i], p.it1[i]);
+    for (size_t j = 0; j < p.items.size(); ++j)
+        std::printf("item %zu %d %d %d\n", j, p.items[j].sys, p.items[j].r0, p.items[j].r1);
+    return 0;
+}
+
 int main() {
-    int capacity, tpp, unroll, bw, count;
-    if (std::scanf("%d %d %d %d %d", &capacity, &tpp, &unroll, &bw, &count) != 5) return 2;
+    char head[16] = {0};
+    if (std::scanf("%15s", head) != 1) return 2;
+    if (!std::strcmp(head, "items")) return items_mode();
+    int capacity = std::atoi(head), tpp, unroll, bw, count;
+    if (std::scanf("%d %d %d %d", &tpp, &unroll, &bw, &count) != 4) return 2;
     std::vector<int64_t> n(count);
     for (int i = 0; i < count; ++i) {
         long long v;

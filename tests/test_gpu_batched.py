@@ -98,6 +98,54 @@ def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
         assert out["wide"][1][i]["status"] == jac.OK
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_schedules_bitwise(jac, dtype, monkeypatch):
+    """The lockstep schedule (one sweep of every system per round, rows dealt
+    out as work items) and the planned one (split systems with their own
+    barriers, a queue of whole systems) give bitwise the same X and counts
+    under the maximum norm: a row's value does not depend on who sweeps it.
+    Covers max_iter = 0 (X = X0), a cap that stops every system, an invalid
+    system among valid ones, and the Euclidean norm (counts and X equal, the
+    distance to rounding)."""
+    import torch
+    shapes = [(4000, 32), (700, 32), (64, 5), (2048, 16), (300, 1), (1500, 9), (1, 1), (33, 3)]
+    sysl = []
+    for idx, (n, k) in enumerate(shapes):
+        A32, _, B32 = _sys32(n, k, 960 + idx)
+        A = dev(A32)
+        x0 = dev(np.random.default_rng(idx).uniform(-1, 1, size=(n, k)).astype(np.float32))
+        sysl.append((A.to(torch.bfloat16) if dtype == "bf16" else A, dev(B32), x0))
+    bad = list(sysl)
+    Bb = sysl[3][1].clone()
+    Bb[17, 2] = float("nan")
+    bad[3] = (sysl[3][0], Bb, sysl[3][2])
+    runs = [(sysl, dict(tol=1e-6, max_iter=200)), (sysl, dict(tol=1e-6, max_iter=0)),
+            (sysl, dict(tol=0.0, max_iter=3)), (bad, dict(tol=1e-6, max_iter=200)),
+            (sysl, dict(tol=1e-6, max_iter=200, norm="l2"))]
+    for r, (batch, kw) in enumerate(runs):
+        out = {}
+        for sched in ("planned", "lockstep"):
+            monkeypatch.setenv("JACOBI_BATCHED_SCHED", sched)
+            say("batched schedule", sched, dtype, r)
+            out[sched] = jac.solve_batched(batch, **kw)
+        monkeypatch.delenv("JACOBI_BATCHED_SCHED")
+        for i in range(len(shapes)):
+            a, b = out["planned"][1][i], out["lockstep"][1][i]
+            assert a["status"] == b["status"] and a["iterations"] == b["iterations"], (r, i, a, b)
+            if b["status"] < 0:
+                assert b["bad_index"] == a["bad_index"]
+                continue
+            assert torch.equal(out["planned"][0][i], out["lockstep"][0][i]), (r, shapes[i])
+            if kw.get("norm") == "l2":
+                assert b["final_delta"] == pytest.approx(a["final_delta"], rel=1e-12)
+            else:
+                assert b["final_delta"] == a["final_delta"]
+            if kw["max_iter"] == 0:
+                assert torch.equal(out["lockstep"][0][i], batch[i][2])
+        if r == 3:
+            assert out["lockstep"][1][3]["status"] == jac.ERR_NONFINITE_INPUT
+
+
 def test_shape_tuning_keeps_results(jac, monkeypatch):
     """The first batch of a class (here 4 x n = 2048, 64 MB per sweep) is timed
     on both kernel shapes before the real run; the tuned runs (first and

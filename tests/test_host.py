@@ -336,6 +336,60 @@ def test_planner_on_the_batched_workload(plan_exe):
             assert r1 - r0 >= 32 or r1 == ns[s]
 
 
+def _items(exe, ns, capacity, tpp=2, elem=4):
+    inp = f"items {capacity} {tpp} {elem} {len(ns)} " + " ".join(str(int(v)) for v in ns)
+    out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True).stdout
+    grid, ranges, items = 0, {}, []
+    for ln in out.splitlines():
+        p = ln.split()
+        if p[0] == "grid":
+            grid = int(p[1])
+        elif p[0] == "range":
+            ranges[int(p[1])] = (int(p[2]), int(p[3]))
+        else:
+            assert int(p[1]) == len(items)
+            items.append(tuple(map(int, p[2:])))
+    return grid, ranges, items
+
+
+def test_lockstep_items_invariants(plan_exe):
+    """Work items of the lockstep schedule: each system's rows covered once,
+    in order, by a contiguous item range; chunks are whole passes of
+    16 * tpp rows except a system's last; systems by decreasing n; item
+    sizes near the target; grid = min(capacity, items)."""
+    rng = np.random.default_rng(5805)
+    cases = [([], 512, 2, 4), ([1], 512, 2, 4), ([16384], 512, 2, 4), ([32768], 256, 4, 2),
+             ([5, 0, 7], 8, 4, 4), ([4096] * 3 + [256], 4, 2, 2)]
+    for _ in range(30):
+        count = int(rng.integers(1, 300))
+        ns = np.exp(rng.uniform(np.log(1), np.log(20000), count)).astype(int)
+        cases.append((list(ns), int(rng.integers(1, 1024)), int(rng.choice([2, 4])),
+                      int(rng.choice([2, 4]))))
+    for ns, cap, tpp, elem in cases:
+        grid, ranges, items = _items(plan_exe, ns, cap, tpp, elem)
+        assert grid == min(max(1, cap), len(items))
+        total = sum(int(v) * int(v) * elem for v in ns)
+        target = min(2 << 20, max(128 << 10, total / (8 * max(1, cap))))
+        seen = []
+        for s_, (a, b) in ranges.items():
+            n = int(ns[s_])
+            assert (b > a) == (n > 0)
+            rows = [items[j] for j in range(a, b)]
+            assert all(it[0] == s_ for it in rows)
+            r = 0
+            for j, (_, r0, r1) in enumerate(rows):
+                assert r0 == r and r1 > r0
+                if j < len(rows) - 1:
+                    assert (r1 - r0) % (16 * tpp) == 0
+                    assert (r1 - r0 - 16 * tpp) * n * elem < target
+                r = r1
+            assert r == n
+            seen.extend(range(a, b))
+        assert sorted(seen) == list(range(len(items)))
+        order = [it[0] for j, it in enumerate(items) if j == 0 or items[j - 1][0] != it[0]]
+        assert [int(ns[i]) for i in order] == sorted((int(ns[i]) for i in order), reverse=True)
+
+
 # ---- serving arena -----------------------------------------------------------
 
 def test_serving_arena_invariants(tmp_path):
