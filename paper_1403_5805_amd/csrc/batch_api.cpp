@@ -114,14 +114,14 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         return JACOBI_ERR_INTERNAL;
     }
 
-    // workspace: per system buf0, buf1 (kt x xld, transposed) and diag (n)
+    // workspace: per system buf0, buf1, bT (kt x xld, transposed) and diag (n)
     std::vector<size_t> off(count);
     size_t ws = 0;
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     auto xld_of = [](int64_t n) { return (n + 63) / 64 * 64; };  // a multiple of every block width
     for (int i = 0; i < count; ++i) {
         off[i] = ws;
-        ws += 2 * align(sizeof(float) * xld_of(items[i].n) * kt) +
+        ws += 3 * align(sizeof(float) * xld_of(items[i].n) * kt) +
               align(sizeof(float) * items[i].n);
     }
     // device metadata: [sys | st | schedule tables (uploaded) | partial sums]
@@ -167,8 +167,9 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         const size_t xb = align(sizeof(float) * xld_of(it.n) * kt);
         S.buf0 = (float*)base;
         S.buf1 = (float*)(base + xb);
+        S.bT = (float*)(base + 2 * xb);
         S.xld = xld_of(it.n);
-        S.diag = (const float*)(base + 2 * xb);
+        S.diag = (const float*)(base + 3 * xb);
         S.n = it.n;
         S.k = (int32_t)it.k;
         if (sched == 1) {
@@ -183,8 +184,6 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         S.tol = o.tol;
         S.rel = rel;
         S.norm = o.norm;
-        const size_t ea = a_dtype == JACOBI_F32 ? 4 : 2;
-        S.aligned = (((uintptr_t)it.A % 16) == 0 && ((size_t)it.lda * ea) % 16 == 0) ? 1 : 0;
         BState& T = hst[i];
         std::memset(&T, 0, sizeof(T));
         T.bad_diag = INT64_MAX;

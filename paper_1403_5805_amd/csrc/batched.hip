@@ -114,8 +114,8 @@ __device__ __forceinline__ uint64_t wmax(uint64_t v) {
 
 // ---------------------------------------------------------------------------
 // Setup: per system, gather alpha_ii, validate (zero / non-finite diagonal,
-// non-finite B or X0), write X0 (or zeros) transposed into buf0 and clear
-// buf1, padding included.  grid = (row blocks, systems).
+// non-finite B or X0), write X0 (or zeros) and B transposed into buf0 and bT
+// and clear buf1, padding included.  grid = (row blocks, systems).
 template <typename TA>
 __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict__ st, int kt) {
     const BSys S = sys[blockIdx.y];
@@ -128,6 +128,7 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
             for (int c = 0; c < kt; ++c) {
                 S.buf0[c * S.xld + i] = 0.0f;
                 S.buf1[c * S.xld + i] = 0.0f;
+                S.bT[c * S.xld + i] = 0.0f;
             }
             continue;
         }
@@ -140,14 +141,15 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
                                    __HIP_MEMORY_SCOPE_AGENT);
         bool bad = false;
         for (int c = 0; c < kt; ++c) {
-            float x0 = 0.0f;
+            float x0 = 0.0f, b = 0.0f;
             if (c < S.k) {
                 if (S.X0) x0 = S.X0[i * S.ldx + c];
-                const float b = S.B[i * S.ldb + c];
+                b = S.B[i * S.ldb + c];
                 if (!isfinite(b) || !isfinite(x0)) bad = true;
             }
             S.buf0[c * S.xld + i] = x0;
             S.buf1[c * S.xld + i] = 0.0f;
+            S.bT[c * S.xld + i] = b;
         }
         if (bad)
             __hip_atomic_fetch_min(&T->bad_rhs, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -178,7 +180,11 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
     const int64_t xld = S.xld;
     const int k = S.k;
     const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
-    const int64_t nbf = S.aligned ? (n / BW) : 0;  // blocks loadable with 16-byte loads
+    // Full blocks are read with 16-byte loads whatever the row alignment (a
+    // row of n FP32 values starts 16-byte aligned only when n % 4 == 0): the
+    // runtime runs kernels in unaligned access mode, where such a load costs
+    // at most one more cache-line access and returns the same values.
+    const int64_t nbf = n / BW;
     // this wave's vector-loadable blocks: b = wave + W * t, t < ntw
     const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
     const int64_t nfull = (ntw / U) * U;
@@ -310,8 +316,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
         if (more) rows_of(arow_next, pr + 16 * TPW);
         preloaded = more && nfull > 0;
         if (preloaded) issue(arow_next, v0, b0, 0);
-        // Remaining blocks of this wave (ragged tail, or every block of
-        // rows that are not 16-byte aligned).
+        // Remaining blocks of this wave (the ragged tail).
         for (int64_t b = wave + W * nfull; b < nb; b += W) {
             float a[TPW][VEC];
 #pragma unroll
@@ -344,11 +349,32 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     red[(((wave * TPW + q) * NT + t) * 4 + v) * 64 + lane] = acc[q][t][v];
+        // Epilogue: thread element u is e = tid + u * W * 64: column cc of
+        // tile (q, t), row ri, so consecutive threads touch consecutive rows
+        // of the transposed iterate and right-hand side.  Its operands are
+        // all requested here, before the barrier, so their latencies overlap
+        // one another and the reduction instead of adding up.
+        constexpr int EPT = TPW * NT * 256 / (W * 64);
+        static_assert(EPT * W * 64 == TPW * NT * 256, "epilogue elements per thread");
+        float e_xo[EPT], e_b[EPT], e_d[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * W * 64;
+            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+            const int q = qt / NT, t = qt - q * NT;
+            const int64_t i = pr + 16 * q + ri;
+            const int c = t * 16 + cc;
+            const bool ok = i < r1 && c < k;
+            const int64_t is = ok ? i : r0;  // a row and column that exist
+            const int cs = ok ? c : 0;
+            e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
+            e_b[u] = *gbl(S.bT + (int64_t)cs * xld + is);
+            e_d[u] = *gbl(S.diag + is);
+        }
         __syncthreads();
-        // Epilogue: thread e takes column cc of tile (q, t), row ri, so
-        // consecutive threads write consecutive rows of the transposed
-        // iterate.
-        for (int e = tid; e < TPW * NT * 256; e += W * 64) {
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * W * 64;
             const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
             const int q = qt / NT, t = qt - q * NT;
             const int l = 16 * (ri >> 2) + cc, v = ri & 3;
@@ -358,8 +384,8 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
             const int64_t i = pr + 16 * q + ri;
             const int c = t * 16 + cc;
             if (i < r1 && c < k) {
-                const float xo = *gbl(xin + (int64_t)c * xld + i);
-                const float xn = (*gbl(S.B + i * S.ldb + c) - s) / *gbl(S.diag + i);
+                const float xo = e_xo[u];
+                const float xn = (e_b[u] - s) / e_d[u];
                 *gout(xout + (int64_t)c * xld + i) = xn;
                 const double dd = fabs((double)xn - (double)xo);
                 const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));

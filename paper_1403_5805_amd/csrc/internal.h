@@ -127,6 +127,7 @@ struct BSys {
     const float* X0;   // caller's initial approximation (ldx), or null for zero
     float* buf0;       // x^(0) on entry (transposed); ping-pong with buf1
     float* buf1;
+    float* bT;         // B transposed (kt x xld, padding zero)
     int64_t xld;       // leading dimension of the transposed iterate (multiple of 32)
     const float* diag;
     int64_t n;
@@ -137,7 +138,6 @@ struct BSys {
     double tol;        // TEST_ABS threshold
     double rel;        // TEST_REL factor
     int32_t norm;      // 0 inf, 1 l2
-    int32_t aligned;   // rows of A 16-byte aligned
     int32_t it0, it1;  // lockstep schedule: the system's work items [it0, it1)
 };
 
