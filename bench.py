@@ -300,6 +300,16 @@ def bench_c1(args):
     return res
 
 
+def _batched_kernel_name(code: int, ta: str, kt: int) -> str:
+    """Kernel that ran a batched solve, from jacobi_info.kernel (bit 0:
+    lockstep schedule, bit 1: deep shape) and its template shape."""
+    deep = bool(code & 2)
+    tpw = 4 if (deep or (kt <= 16 and ta == "float")) else 2
+    name = "k_rounds" if code & 1 else "k_batched"
+    return (f"{name}<{ta},KT={kt},W=4,TPW={tpw},U=1> ({'deep, 1' if deep else 'wide, 2'} "
+            f"workgroup(s) per CU; {'lockstep' if code & 1 else 'planned'} schedule)")
+
+
 def bench_c3(args):
     """256 FP32 systems, n log-uniform [256, 4096], k = 32, tol 1e-6: one
     persistent batched launch per step."""
@@ -350,7 +360,7 @@ def bench_c3(args):
     res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
     res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                       "kernel": "k_batched<float,KT=32,W=4,TPW=2,U=1>, two 16-byte loads per lane and block",
+                       "kernel": _batched_kernel_name(infos[0]["kernel"], "float", 32),
                        "mfma_tflops": round(tfs, 2),
                        "mfma_frac_of_157_3": round(tfs / 157.3, 4),
                        "launch_device_ms": round(dev_ms, 3)}

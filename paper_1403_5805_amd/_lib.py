@@ -57,7 +57,7 @@ class Info(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("iterations", ctypes.c_int32),
         ("outer_iterations", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
         ("bad_index", ctypes.c_int64),
         ("final_delta", ctypes.c_double),
         ("rel_residual", ctypes.c_double),
@@ -70,7 +70,7 @@ class Info(ctypes.Structure):
         return {name: getattr(self, name) for name in _INFO_KEYS}
 
 
-_INFO_KEYS = tuple(name for name, _ in Info._fields_ if name != "reserved")
+_INFO_KEYS = tuple(name for name, _ in Info._fields_)
 
 
 class System(ctypes.Structure):

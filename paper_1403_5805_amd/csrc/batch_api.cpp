@@ -33,11 +33,13 @@ static double bits_to_double(uint64_t b) {
 }
 
 // Per-system outcomes from the device states after a launch.
-static void decode_states(const BState* hst, int32_t count, float ms, jacobi_info* infos) {
+static void decode_states(const BState* hst, int32_t count, float ms, int32_t kernel,
+                          jacobi_info* infos) {
     for (int i = 0; i < count; ++i) {
         jacobi_info& inf = infos[i];
         const BState& T = hst[i];
         inf.device_ms = ms;
+        inf.kernel = kernel;
         inf.rel_residual = -1.0;
         inf.bad_index = -1;
         if (T.bad_diag != INT64_MAX) {
@@ -262,7 +264,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     }
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
-    decode_states(hst.data(), count, ms, infos);
+    decode_states(hst.data(), count, ms, (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0), infos);
     return JACOBI_OK;
 }
 
