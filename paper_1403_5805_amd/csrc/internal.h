@@ -80,6 +80,11 @@ struct SweepArgs {
     const float* dlt;  // correction d (float, ld k) added to xin while staging, or null
     double* r64;       // residual out (double, ld k)
     float* rlo;        // residual out (float, ld k)
+    // residual pass: also write A rounded to FP32 / BF16 (lo_dtype 1 / 2)
+    // into alo (ld_lo), or nothing when alo is null
+    void* alo;
+    int64_t ld_lo;
+    int32_t lo_dtype;
 };
 
 // Host-side launch configuration chosen per call.

@@ -11,8 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <cmath>
 
 #include "batch.h"
 #include "ctx.h"
@@ -99,9 +100,16 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         set_error("input validation failed at row %lld", (long long)info->bad_index);
         return vs;
     }
-    // A_lo = round(A), its diagonal, and the inner-solve launch shape.
-    HIP_TRY(launch_convert((const double*)A, lda, n, lo, c->alo.p, ld_lo, s));
-    HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
+    // A_lo = round(A) and its diagonal.  With one column the first residual
+    // pass writes A_lo while it streams A (one read of the FP64 matrix
+    // instead of two); the MFMA residual leaves it to the conversion kernel.
+    bool fuse_convert = !mfma_resid;
+    if (const char* env = getenv("JACOBI_REFINE_FUSED_CONVERT"))
+        fuse_convert = fuse_convert && strcmp(env, "0") != 0;
+    if (!fuse_convert) {
+        HIP_TRY(launch_convert((const double*)A, lda, n, lo, c->alo.p, ld_lo, s));
+        HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
+    }
     const LaunchCfg rcfg = residual_cfg(n, (int)k, c->num_cus);
     const LaunchCfg icfg = default_cfg(lo, n, (int)k, c->num_cus);
 
@@ -164,7 +172,14 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         ra.dlt = dlt;
         ra.r64 = (double*)c->r64.p;
         ra.rlo = (float*)c->rlo.p;
+        const bool write_lo = fuse_convert && outer == 0;
+        if (write_lo) {
+            ra.alo = c->alo.p;
+            ra.ld_lo = ld_lo;
+            ra.lo_dtype = lo;
+        }
         HIP_TRY(launch_residual(ra, rcfg, s));
+        if (write_lo) HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
         HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *stop = c->h_ctl->stop;

@@ -32,6 +32,7 @@
 #include <stdlib.h>
 
 #include "internal.h"
+#include "round.h"
 
 namespace jac {
 
@@ -259,11 +260,16 @@ __device__ __forceinline__ void stage_x(TX* __restrict__ xs, const TX* __restric
 // W waves together read W consecutive 1 KiB pieces of each row per load.
 // MODE 0 skips j == i (sec. 2: the sum runs over j != i); MODE 1 (residual)
 // keeps every term.
+//
+// MODE 1 with lo_dtype != 0 also stores every A value it loads, rounded to
+// FP32 (lo_dtype 1) or BF16 (2), at the same place of alo (leading dimension
+// ld_lo): a pass reads each value once, so the copy is written exactly once.
 template <typename TA, typename TX, int KT, int R, int U, int W, int MODE>
 __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restrict__ A, int64_t lda,
                                            int64_t n, int64_t g, int64_t c0, int64_t cl,
                                            const TX* __restrict__ xs, int lane, int wave,
-                                           bool aligned) {
+                                           bool aligned, void* alo = nullptr, int64_t ld_lo = 0,
+                                           int lo_dtype = 0) {
     constexpr int VEC = Elem<TA>::vec;
     constexpr int SPAN = 64 * VEC;
     constexpr int NV = (VEC * KT * (int)sizeof(TX)) / 16;  // LDS 16-byte reads per load
@@ -291,6 +297,28 @@ __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restric
         TX a[R][VEC];
 #pragma unroll
         for (int r = 0; r < R; ++r) unpack16<TA, TX>(v[r], a[r]);
+        if constexpr (MODE == 1 && sizeof(TA) == 8 && VEC == 2) {
+            if (lo_dtype != 0) {
+                const int64_t col = c0 + cbase + (int64_t)lane * VEC;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (g + r >= n) continue;
+                    const double d0 = __longlong_as_double(
+                        (long long)(((uint64_t)v[r].y << 32) | v[r].x));
+                    const double d1 = __longlong_as_double(
+                        (long long)(((uint64_t)v[r].w << 32) | v[r].z));
+                    if (lo_dtype == 2) {
+                        const uint32_t w = (uint32_t)f64_to_bf16_rne(d0) |
+                                           ((uint32_t)f64_to_bf16_rne(d1) << 16);
+                        *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(alo) +
+                                                     (g + r) * ld_lo + col) = w;
+                    } else {
+                        *reinterpret_cast<float2*>(static_cast<float*>(alo) + (g + r) * ld_lo +
+                                                   col) = make_float2((float)d0, (float)d1);
+                    }
+                }
+            }
+        }
         if (MODE == 0 && cbase < dlo + R && dlo < cbase + SPAN) {
             const int64_t col = cbase + (int64_t)lane * VEC;
 #pragma unroll
@@ -335,7 +363,18 @@ __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restric
         for (int c = 0; c < KT; ++c) xv[c] = xs[col * KT + c];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            TX a = widen<TA, TX>(rowp[r][col - lane * VEC]);
+            const TA raw = rowp[r][col - lane * VEC];
+            if constexpr (MODE == 1 && sizeof(TA) == 8) {
+                if (lo_dtype != 0 && g + r < n) {
+                    const double d = (double)raw;
+                    if (lo_dtype == 2)
+                        static_cast<uint16_t*>(alo)[(g + r) * ld_lo + c0 + col] =
+                            f64_to_bf16_rne(d);
+                    else
+                        static_cast<float*>(alo)[(g + r) * ld_lo + c0 + col] = (float)d;
+                }
+            }
+            TX a = widen<TA, TX>(raw);
             if (MODE == 0 && col == dlo + r) a = (TX)0;
 #pragma unroll
             for (int c = 0; c < KT; ++c) acc[r][c] = tx_fma(a, xv[c], acc[r][c]);
@@ -477,6 +516,8 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
     const TX* xsrc = xin + cb;
     const float* dsrc = (MODE == 1 && p.dlt) ? (p.dlt + cb) : nullptr;
     const bool contiguous = (kp == KT);
+    // the residual pass writes the reduced copy of A once (first column group)
+    const bool cvt = MODE == 1 && p.alo != nullptr && blockIdx.y == 0;
 
     auto stage = [&](int64_t c0, int64_t cl) {
         if (contiguous) {
@@ -522,7 +563,8 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
 #pragma unroll
                         for (int c = 0; c < KT; ++c) acc[r][c] = (TX)0;
                     accumulate<TA, TX, KT, R, U, W, MODE>(acc, A, p.lda, n, g, c0, cl, xs, lane,
-                                                          wave, aligned);
+                                                          wave, aligned, p.alo, p.ld_lo,
+                                                          cvt ? p.lo_dtype : 0);
 #pragma unroll
                     for (int r = 0; r < R; ++r)
 #pragma unroll

@@ -132,3 +132,28 @@ def test_c4_full_size(jac):
     print(f"c4: outer={info['outer_iterations']} inner={info['iterations']} "
           f"rel_res={info['rel_residual']:.3e} err_vs_xref={rel_err(x, xr):.3e} "
           f"device_ms={info['device_ms']:.1f}", flush=True)
+
+
+@pytest.mark.parametrize("lo", ["bf16", "f32"])
+@pytest.mark.parametrize("n,pad", [(2, 0), (37, 1), (1024, 0), (1031, 1), (9000, 0)])
+def test_fused_conversion_bitwise(jac, monkeypatch, lo, n, pad):
+    """With one right-hand side the first residual pass writes A_lo while it
+    streams A.  The reduced copy equals the conversion kernel's bitwise, so the
+    whole refinement (X, counts, residual) is bitwise the same as with a
+    separate conversion pass; odd leading dimensions take the unaligned
+    (element) path, n = 9000 several staged x chunks."""
+    import torch
+    A, _, B = synth.dominant(n, 1, 4100 + n + pad, synth.MULTIPLICATIVE, 0.5, 1.0)
+    Ad = _padded(A, pad)
+    Bd = dev(B)
+    out = {}
+    for fused in ("0", "1"):
+        monkeypatch.setenv("JACOBI_REFINE_FUSED_CONVERT", fused)
+        say("fused conversion", lo, n, pad, fused)
+        out[fused] = jac.solve(Ad, Bd, mode="refine", sweep_dtype=lo)
+    monkeypatch.delenv("JACOBI_REFINE_FUSED_CONVERT")
+    (X0, i0), (X1, i1) = out["0"], out["1"]
+    assert i1["status"] == jac.OK, i1
+    for key in ("status", "iterations", "outer_iterations", "rel_residual", "final_delta"):
+        assert i0[key] == i1[key], (key, i0, i1)
+    assert torch.equal(X0, X1)
