@@ -9,12 +9,14 @@
 //     work on the same tiles and split the columns (wave w takes every W-th
 //     block), and their partial tiles are added in wave order through LDS, so
 //     even a system of a few hundred rows keeps every wave streaming;
-//   * lane l loads row (l % 16) of a tile, 32 bytes of consecutive columns
-//     (8 FP32 or 16 BF16 values, two 16-byte loads) at column group l / 16,
-//     so the four groups read one full 128-byte line of each row per block
-//     (a probe measured 5.5 TB/s for this pattern against 3.6 TB/s for
-//     16-byte pieces, which split every line between two waves); one block
-//     feeds 8 (FP32) or 16 (BF16) MFMA k-steps;
+//   * lane l loads row (l % 16) of a tile with two 16-byte loads; in load j
+//     the four lane groups g = l / 16 read bytes 64 j + 16 g of the block, so
+//     each load covers 64 contiguous bytes of every row and the wave reads one
+//     full 128-byte line of each row per block (a probe measured 5.5 TB/s for
+//     whole lines per wave against 3.6 TB/s for lines split between two
+//     waves; on rows that are not 16-byte aligned the contiguous 64-byte runs
+//     measured 10% faster than 32-byte runs per lane); one block feeds 8
+//     (FP32) or 16 (BF16) MFMA k-steps;
 //   * the iterate is kept transposed in global memory (column c of X is a
 //     contiguous row of xld floats, zero padded), so the matching B operand
 //     of 4 k-steps is one 16-byte load that hits the L2 (X is small and every
@@ -175,6 +177,11 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
     constexpr int NT = KT / 16;                // 16-column output tiles
     constexpr int NS = VEC / 4;                // 4-step MFMA groups per block
     const int lane = tid & 63, grp = lane >> 4, li = lane & 15;
+    // Lane layout of a block: load j of lane group grp holds columns
+    // j * 4 * V16 + grp * V16 + [0, V16), so the four groups of one load read
+    // 64 contiguous bytes of a row.  Element e of a lane sits at column
+    // grp * V16 + ecol(e) of the block; the B operand follows the same map.
+    auto ecol = [](int e) { return (e / V16) * 4 * V16 + e % V16; };
     const TA* A = reinterpret_cast<const TA*>(S.A);
     const int64_t n = S.n;
     const int64_t xld = S.xld;
@@ -191,7 +198,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
     gptr<float> xrow[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-        xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + VEC * grp);
+        xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + V16 * grp);
     // Row pointers of the pass starting at row pr.  Rows past the job
     // (a short last pass) re-read the job's last row, which the cache
     // serves, and are discarded.
@@ -200,7 +207,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
         for (int q = 0; q < TPW; ++q) {
             int64_t ri = pr + 16 * q + li;
             if (ri >= r1) ri = r1 - 1;
-            rows[q] = gbl(A + ri * S.lda + VEC * grp);
+            rows[q] = gbl(A + ri * S.lda + V16 * grp);
         }
     };
     auto load_b = [&](f32x4 (&bx)[NT][NS], int64_t b) {
@@ -208,7 +215,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int sg = 0; sg < NS; ++sg)
-                bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + 4 * sg);
+                bx[t][sg] = *(gptr<f32x4>)(xrow[t] + b * BW + ecol(4 * sg));
     };
     // Loads of U blocks starting at this wave's block t0.
     auto issue = [&](const gptr<TA> (&rows)[TPW], u32x4 (&v)[U][TPW][LPL],
@@ -221,7 +228,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 #pragma unroll
                 for (int j = 0; j < LPL; ++j)
                     v[u][q][j] = __builtin_nontemporal_load(
-                        (gptr<u32x4>)(rows[q] + b * BW + j * V16));
+                        (gptr<u32x4>)(rows[q] + b * BW + j * 4 * V16));
             load_b(bx[u], b);
         }
     };
@@ -250,7 +257,10 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 if (b == rt[q] / BW) {
-                    const int dpos = (int)(rt[q] - b * BW) + li - VEC * grp;
+                    const int rel = (int)(rt[q] - b * BW) + li;  // diagonal column in the block
+                    const int rem = rel % (4 * V16);
+                    const int dpos =
+                        rem / V16 == grp ? (rel / (4 * V16)) * V16 + rem % V16 : -1;
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) a[q][e] = (e == dpos) ? 0.0f : a[q][e];
                 }
@@ -325,14 +335,14 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 #pragma unroll
                     for (int j = 0; j < LPL; ++j) {
                         const u32x4 v = __builtin_nontemporal_load(
-                            (gptr<u32x4>)(arow[q] + b * BW + j * V16));
+                            (gptr<u32x4>)(arow[q] + b * BW + j * 4 * V16));
                         unpack<TA>(v, a[q] + j * V16);
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        const int64_t col = b * BW + VEC * grp + e;
-                        a[q][e] = col < n ? widen1<TA>(arow[q][b * BW + e]) : 0.0f;
+                        const int64_t col = b * BW + V16 * grp + ecol(e);
+                        a[q][e] = col < n ? widen1<TA>(arow[q][b * BW + ecol(e)]) : 0.0f;
                     }
                 }
             }
