@@ -25,12 +25,16 @@
 //   * the diagonal term is masked in the A operand (sum over j != i);
 //   * the reduced tile is the epilogue's input: division by a_ii, the
 //     distance max|x_new - x_old| (or its Euclidean form) and the stop test.
-// Systems are planned on the host: a large system is split over several
-// workgroups that meet at a per-system barrier (atomic counter) after every
-// sweep; small systems are owned whole by one workgroup (barrier = LDS
-// barrier) and packed several per workgroup.  The launch is cooperative, so
-// every workgroup is resident and the barrier waits always end; a wall-clock
-// bound turns a stuck wait into an error instead of a hang.
+// Two schedules run the same row sweep (sweep_rows):
+//   * lockstep (k_rounds, the default): round r is sweep r of every running
+//     system; rows of all systems are dealt out as work items from one
+//     atomic ticket counter, one grid barrier closes each round;
+//   * planned (k_batched): a large system is split over several workgroups
+//     that meet at a per-system barrier (atomic counter) after every sweep;
+//     small systems are owned whole by one workgroup and taken from a queue.
+// Launches are cooperative, so every workgroup is resident and the barrier
+// waits always end; a wall-clock bound turns a stuck wait into an error
+// instead of a hang.
 #include <math.h>
 #include <stdint.h>
 
