@@ -20,7 +20,7 @@ from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVA
                    ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
                    F64, NOT_CONVERGED, OK, PENDING, Info, Options)
 
-__all__ = ["solve", "solve_batched", "Server", "status_string", "last_error", "Context",
+__all__ = ["solve", "solve_batched", "Batch", "Server", "status_string", "last_error", "Context",
            "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
            "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
            "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
@@ -201,5 +201,5 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
     return out, d
 
 
-from .batched import solve_batched  # noqa: E402
+from .batched import Batch, solve_batched  # noqa: E402
 from .serve import Server  # noqa: E402

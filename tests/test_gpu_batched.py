@@ -283,3 +283,25 @@ def test_strided_out_with_x0(jac):
     assert info["status"] == jac.OK
     X, _ = jac.solve(A, B, x0, tol=1e-6, max_iter=200)
     assert torch.equal(X, Y)
+
+
+def test_prepared_batch(jac):
+    """A Batch marshals its systems once; every solve() equals a fresh
+    solve_batched bitwise, and sees new contents of B written in place
+    between solves."""
+    import torch
+    shapes = [(300, 32), (1201, 7), (64, 1)]
+    sysl = []
+    for idx, (n, k) in enumerate(shapes):
+        A32, _, B32 = _sys32(n, k, 990 + idx)
+        sysl.append((dev(A32), dev(B32)))
+    batch = jac.Batch(sysl, ctx=None)
+    for rep in range(3):
+        say("prepared batch", rep)
+        xs, infos = batch.solve(tol=1e-6, max_iter=300)
+        ref, rinfos = jac.solve_batched(sysl, tol=1e-6, max_iter=300)
+        for X, Y, a, b in zip(xs, ref, infos, rinfos):
+            assert torch.equal(X, Y)
+            assert a["iterations"] == b["iterations"] and a["status"] == b["status"] == jac.OK
+        for _, B in sysl:
+            B.mul_(0.5)  # the next solve reads the new right-hand sides
