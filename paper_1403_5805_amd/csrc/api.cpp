@@ -87,8 +87,8 @@ jacobi_status ctx_init(jacobi_ctx* c, int device) {
     c->num_cus = prop.multiProcessorCount;
     if (hipSetDevice(device) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipMalloc(&c->ctl, sizeof(Ctl)) != hipSuccess) return JACOBI_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&c->slots, 2 * sizeof(Slot)) != hipSuccess) return JACOBI_ERR_OUT_OF_MEMORY;
-    if (hipMalloc(&c->parts, 2 * sizeof(double) * kMaxParts) != hipSuccess)
+    if (hipMalloc(&c->slots, 3 * sizeof(Slot)) != hipSuccess) return JACOBI_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(&c->parts, 3 * sizeof(double) * kMaxParts) != hipSuccess)
         return JACOBI_ERR_OUT_OF_MEMORY;
     if (hipHostMalloc(&c->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
         return JACOBI_ERR_OUT_OF_MEMORY;
@@ -251,6 +251,9 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
             HIP_TRY(launch_sweep(a_dtype, args, cfg, s));
             if (profile) HIP_TRY(hipEventRecord(c->prof_ev[2 * (q - 1) + 1], s));
         }
+        // each launch decides its predecessor; the group's last one is decided
+        // here (a no-op when the phase has already stopped)
+        HIP_TRY(launch_decide(args, cfg.grid * ((args.k + 31) / 32), s));
         HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const Ctl& h = *c->h_ctl;

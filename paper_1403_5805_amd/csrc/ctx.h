@@ -40,8 +40,8 @@ struct jacobi_ctx {
     int num_cus = 256;
     std::mutex mu;
     jac::Ctl* ctl = nullptr;      // device control block
-    jac::Slot* slots = nullptr;   // device reduction slots [2]
-    double* parts = nullptr;      // device partial sums [2][kMaxParts]
+    jac::Slot* slots = nullptr;   // device reduction slots [3]
+    double* parts = nullptr;      // device partial sums [3][kMaxParts]
     jac::Ctl* h_ctl = nullptr;    // pinned host mirror of ctl
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     std::vector<hipEvent_t> prof_ev;

@@ -39,7 +39,7 @@ struct alignas(64) Ctl {
     uint32_t pad1;
 };
 
-// Per-sweep reduction slot (two of them, used alternately).
+// Per-launch reduction slot (three of them, launch seq uses slot seq % 3).
 struct alignas(64) Slot {
     uint64_t dmax_bits;  // atomic max of |x_new - x_old| (double bits, >= 0; NaN wins)
     uint64_t xmax_bits;  // atomic max of |x_new|
@@ -69,8 +69,8 @@ struct SweepArgs {
     int64_t rows_per_wg;  // rows owned by one workgroup (contiguous block)
     int32_t kpad;      // leading dimension of the iterate buffers (>= k)
     Ctl* ctl;
-    Slot* slots;       // [2]
-    double* parts;     // [2][kMaxParts]
+    Slot* slots;       // [3], launch seq publishes into slot seq % 3
+    double* parts;     // [3][kMaxParts]
     double tol;        // TEST_ABS threshold
     double rel;        // TEST_REL / TEST_RESID factor
     double bnorm;      // TEST_RESID: ||b||_2
@@ -105,6 +105,9 @@ hipError_t launch_setup(int32_t a_dtype, const void* A, int64_t lda, const void*
 hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cfg,
                         hipStream_t s);
 hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s);
+// Stop decision for launch a.seq (sweep a.sweep) of a phase, whose grid had
+// `total` workgroups, when no later launch takes it; records it in a.ctl.
+hipError_t launch_decide(const SweepArgs& a, int total, hipStream_t s);
 hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
                           int64_t ldo, hipStream_t s);
 hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64_t n,

@@ -179,6 +179,7 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
             ra.lo_dtype = lo;
         }
         HIP_TRY(launch_residual(ra, rcfg, s));
+        HIP_TRY(launch_decide(ra, rcfg.grid * (int)((k + 31) / 32), s));
         if (write_lo) HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
         HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));

@@ -140,7 +140,7 @@ __global__ void k_init_ctl(Ctl* ctl, Slot* slots, int full) {
             ctl->bad_rhs = INT64_MAX;
             ctl->setup_ticket = 0;
         }
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < 3; ++s) {
             slots[s].dmax_bits = 0;
             slots[s].xmax_bits = 0;
             slots[s].ticket = 0;
@@ -383,14 +383,21 @@ __device__ __forceinline__ void accumulate(TX (&acc)[R][KT], const TA* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Grid-wide reduction of the per-lane distance statistics and the stop
-// decision by the last workgroup.  All threads of the workgroup must call it.
+// Distance statistics and the stop decision.
+//
+// A launch only publishes: each workgroup folds its lanes' maxima (and sum
+// of squares) and adds them to the launch's slot with relaxed atomics
+// (slot = launch number % 3), nothing waits for a reply.  The decision for a
+// launch is taken by every workgroup of the next launch of the phase as it
+// starts (the launch boundary orders it after all of the previous launch's
+// atomics), or, after the last launch of a group, by k_decide.  All
+// workgroups read the same values and decide alike; workgroup 0 records the
+// outcome in the control block.  All threads of the workgroup must call.
 template <int W>
 __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax, uint64_t xmax,
                                               double sq) {
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
-    __shared__ uint32_t s_last;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool need_sum = (p.norm == 1) || (p.test == TEST_RESID);
     dmax = wave_max_u64(dmax);
@@ -402,10 +409,9 @@ __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax,
         red_s[wave] = sq;
     }
     __syncthreads();
-    const int total = gridDim.x * gridDim.y;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    Slot* sl = &p.slots[p.seq & 1];
-    double* parts = p.parts + (size_t)(p.seq & 1) * kMaxParts;
+    Slot* sl = &p.slots[p.seq % 3];
+    double* parts = p.parts + (size_t)(p.seq % 3) * kMaxParts;
     if (tid == 0) {
         uint64_t D = 0, M = 0;
         double S = 0.0;
@@ -418,31 +424,39 @@ __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax,
             __hip_atomic_store(&parts[bid], S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_max(&sl->xmax_bits, M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t t =
-            __hip_atomic_fetch_add(&sl->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (uint32_t)(total - 1)) ? 1u : 0u;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // This is the last workgroup: every other one has published its share.
+}
+
+// The stop decision for launch `seq` of the phase (logical sweep `sweep`),
+// whose `total` workgroups have all finished.  Returns STOP_* (the same in
+// every thread); when `record`, thread 0 writes the outcome into the control
+// block.  All threads of the workgroup must call.
+template <int W>
+__device__ __forceinline__ uint32_t decide(const SweepArgs& p, int32_t seq, int32_t sweep,
+                                           int total, bool record) {
+    __shared__ double red_s[W];
+    __shared__ uint32_t s_flag;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool need_sum = (p.norm == 1) || (p.test == TEST_RESID);
+    const Slot* sl = &p.slots[seq % 3];
+    const double* parts = p.parts + (size_t)(seq % 3) * kMaxParts;
     double S = 0.0;
     if (need_sum) {
+        // fixed order: thread t adds parts t, t + W*64, ...; then lanes and
+        // waves in order
         for (int b = tid; b < total; b += W * 64)
             S += __hip_atomic_load(&parts[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         S = wave_sum(S);
-        __syncthreads();
         if (lane == 0) red_s[wave] = S;
         __syncthreads();
         S = 0.0;
         for (int w = 0; w < W; ++w) S += red_s[w];
     }
     if (tid == 0) {
-        const double dm =
-            bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        const double xm =
-            bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+        const double xm = bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
         uint32_t st = STOP_RUNNING;
         double delta;
         if (p.test == TEST_RESID) {
@@ -459,23 +473,32 @@ __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax,
             else if (p.test == TEST_ABS ? (delta < p.tol) : (delta <= p.rel * xm))
                 st = STOP_CONVERGED;
         }
-        Ctl* c = p.ctl;
-        __hip_atomic_store(&c->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&c->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&c->sweeps_done, p.sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (st != STOP_RUNNING) {
-            __hip_atomic_store(&c->stop_sweep, p.sweep, __ATOMIC_RELAXED,
+        if (record) {
+            Ctl* c = p.ctl;
+            __hip_atomic_store(&c->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c->stop, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->sweeps_done, sweep, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (st != STOP_RUNNING) {
+                __hip_atomic_store(&c->stop_sweep, sweep, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&c->stop, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
-        // Clear the other slot for the next launch of this phase.
-        Slot* o = &p.slots[(p.seq + 1) & 1];
-        __hip_atomic_store(&o->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&o->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&o->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = st;
     }
+    __syncthreads();
+    return s_flag;
+}
+
+// Decision for the last launch of a group (launch p.seq, logical sweep
+// p.sweep) when no later launch of the phase takes it; a no-op once the
+// phase has stopped.  One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_decide(SweepArgs p, int total) {
+    if (ld_stop(p.ctl) != STOP_RUNNING) return;
+    decide<4>(p, p.seq, p.sweep, total, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,6 +525,22 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     TX* xs = reinterpret_cast<TX*>(lds_raw);
     if (ld_stop(p.ctl) != STOP_RUNNING) return;
+    if (p.seq > 1) {
+        // the previous launch's outcome: every workgroup decides alike
+        const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+        if (decide<W>(p, p.seq - 1, p.sweep - 1, gridDim.x * gridDim.y, first) !=
+            STOP_RUNNING)
+            return;
+        // launch seq + 1 will publish into slot (seq + 1) % 3, last used by
+        // launch seq - 2, whose decision launch seq - 1 took
+        if (first && threadIdx.x == 0) {
+            Slot* o = &p.slots[(p.seq + 1) % 3];
+            __hip_atomic_store(&o->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&o->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = p.n;
@@ -763,6 +802,11 @@ hipError_t launch_sweep(int32_t a_dtype, const SweepArgs& a, const LaunchCfg& cf
         case 2: return launch_kt<bf16_t, float, 0>(p, cfg, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_decide(const SweepArgs& a, int total, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, a, total);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t s) {
