@@ -431,6 +431,9 @@ __device__ __forceinline__ void finish_launch(const SweepArgs& p, uint64_t dmax,
 // whose `total` workgroups have all finished.  Returns STOP_* (the same in
 // every thread); when `record`, thread 0 writes the outcome into the control
 // block.  All threads of the workgroup must call.
+//
+// The control block's stop flag is read with the slot: when the phase has
+// already stopped, that flag is returned and nothing is recorded.
 template <int W>
 __device__ __forceinline__ uint32_t decide(const SweepArgs& p, int32_t seq, int32_t sweep,
                                            int total, bool record) {
@@ -453,10 +456,12 @@ __device__ __forceinline__ uint32_t decide(const SweepArgs& p, int32_t seq, int3
         for (int w = 0; w < W; ++w) S += red_s[w];
     }
     if (tid == 0) {
+        const uint32_t prior = ld_stop(p.ctl);
         const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT));
         const double xm = bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT));
+        if (prior != STOP_RUNNING) record = false;
         uint32_t st = STOP_RUNNING;
         double delta;
         if (p.test == TEST_RESID) {
@@ -487,7 +492,7 @@ __device__ __forceinline__ uint32_t decide(const SweepArgs& p, int32_t seq, int3
                 __hip_atomic_store(&c->stop, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        s_flag = st;
+        s_flag = prior != STOP_RUNNING ? prior : st;
     }
     __syncthreads();
     return s_flag;
@@ -497,7 +502,6 @@ __device__ __forceinline__ uint32_t decide(const SweepArgs& p, int32_t seq, int3
 // p.sweep) when no later launch of the phase takes it; a no-op once the
 // phase has stopped.  One workgroup of 256 threads.
 __global__ __launch_bounds__(256) void k_decide(SweepArgs p, int total) {
-    if (ld_stop(p.ctl) != STOP_RUNNING) return;
     decide<4>(p, p.seq, p.sweep, total, true);
 }
 
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs p) {
     __shared__ TX red[P * KT * W];
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     TX* xs = reinterpret_cast<TX*>(lds_raw);
-    if (ld_stop(p.ctl) != STOP_RUNNING) return;
+    if (p.seq == 1 && ld_stop(p.ctl) != STOP_RUNNING) return;
     if (p.seq > 1) {
         // the previous launch's outcome: every workgroup decides alike
         const bool first = blockIdx.x == 0 && blockIdx.y == 0;
