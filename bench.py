@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM bytes per sweep launch at n = 16384 from the FETCH_SIZE / WRITE_SIZE
 # counter runs (scaled by a 1 GiB reference copy), valid for the sweep source
 # with this sha256 prefix only.
-SWEEP_TRAFFIC = {"sha256_prefix": "76dbed1cf5704daa", "n": 16384, "bytes": 1074581529}
+SWEEP_TRAFFIC = {"sha256_prefix": "c8315b341a0ac5d7", "n": 16384, "bytes": 1074596646}
 
 
 def _sweep_traffic(n: int):
