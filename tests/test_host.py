@@ -210,6 +210,9 @@ def test_binding_refuses_host_tensors(lib):
         jac.solve(A, b)
     with pytest.raises(ValueError, match="GPU tensor"):
         jac.solve_batched([(A.float(), b.float())])
+    with pytest.raises(ValueError, match="GPU tensor"):
+        jac.Batch([(A.float(), b.float())])
+    assert jac.Batch([]).solve() == ([], [])
     with pytest.raises(TypeError):
         jac.solve(A.to(torch.int32), b)
     with pytest.raises(ValueError):
