@@ -693,10 +693,14 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                     __hip_atomic_fetch_max(&st->xmax[0], M, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
-                const uint32_t t = __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL,
+                // Release only: an acquire invalidates the L2 of the XCD, which
+                // holds the iterates every item reads, so only the item that
+                // completes the system's round takes one.
+                const uint32_t t = __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_RELEASE,
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (t + 1 == (uint32_t)(S.it1 - S.it0)) {
                     // the last item of this system's round: the stop test
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     if (bad) {
                         __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
