@@ -417,8 +417,9 @@ def bench_c4(args):
     err_true = float(np.abs(out.cpu().numpy() - Xt[:, 0]).max() / np.abs(Xt).max())
     inner_b = 2 * n * n + 12 * n
     resid_b = 8 * n * n + 24 * n
-    # A_lo = RNE(A): written (2 bytes per value) by the first residual pass,
-    # which reads A for the residual anyway
+    # From x0 = 0 the first residual is B and reads no A, while A_lo = RNE(A)
+    # reads A once and writes 2 bytes per value: counted as one residual pass
+    # (8 n^2, in outer_iterations) plus the 2 n^2 written
     convert_b = 2 * n * n
     tot_b = info["iterations"] * inner_b + info["outer_iterations"] * resid_b + convert_b
     dev_ms = info["device_ms"]
@@ -437,8 +438,8 @@ def bench_c4(args):
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(tot_b / (dev_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                        "traffic": None,
-                       "kernel": "whole refinement call (residual passes, the first one "
-                                 "also writing the BF16 copy of A; BF16 sweeps)"}
+                       "kernel": "whole refinement call (BF16 copy of A, FP64 residual "
+                                 "passes, BF16 sweeps)"}
     res["cpu_baseline"] = None
     ctx.close()
     return res

@@ -88,4 +88,30 @@ hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dt
     return hipGetLastError();
 }
 
+// The first residual of a refinement that starts from x = 0: r = B exactly
+// (B - A 0), kept in FP64 (r64) and rounded to FP32 (rlo), leading dimension
+// kp, columns [0, k).
+__global__ void k_rhs_residual(const double* __restrict__ B, int64_t ldb, int64_t n, int k,
+                               int64_t kp, double* __restrict__ r64, float* __restrict__ rlo) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * k; e += stride) {
+        const int64_t i = e / k;
+        const int c = (int)(e % k);
+        const double b = B[i * ldb + c];
+        r64[i * kp + c] = b;
+        rlo[i * kp + c] = (float)b;
+    }
+}
+
+hipError_t launch_rhs_residual(const double* B, int64_t ldb, int64_t n, int32_t k, int64_t kp,
+                               double* r64, float* rlo, hipStream_t s) {
+    const int threads = 256;
+    int64_t blocks = (n * k + threads - 1) / threads;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_rhs_residual, dim3((unsigned)blocks), dim3(threads), 0, s, B, ldb, n, k,
+                       kp, r64, rlo);
+    return hipGetLastError();
+}
+
 }  // namespace jac

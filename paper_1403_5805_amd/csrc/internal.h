@@ -110,6 +110,9 @@ hipError_t launch_residual(const SweepArgs& a, const LaunchCfg& cfg, hipStream_t
 hipError_t launch_decide(const SweepArgs& a, int total, hipStream_t s);
 hipError_t launch_convert(const double* A, int64_t lda, int64_t n, int32_t to_dtype, void* out,
                           int64_t ldo, hipStream_t s);
+// r = B (the residual at x = 0) into r64 (FP64) and rlo (FP32), ld kp.
+hipError_t launch_rhs_residual(const double* B, int64_t ldb, int64_t n, int32_t k, int64_t kp,
+                               double* r64, float* rlo, hipStream_t s);
 hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64_t n,
                               void* out, hipStream_t s);
 hipError_t launch_bnorm(const double* B, int64_t ldb, int64_t n, int32_t k, double* out,

@@ -100,10 +100,12 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         set_error("input validation failed at row %lld", (long long)info->bad_index);
         return vs;
     }
-    // A_lo = round(A) and its diagonal.  With one column the first residual
+    // A_lo = round(A) and its diagonal.  From x0 = 0 the first residual is B
+    // itself and reads no A.  Otherwise, with one column, the first residual
     // pass writes A_lo while it streams A (one read of the FP64 matrix
     // instead of two); the MFMA residual leaves it to the conversion kernel.
-    bool fuse_convert = !mfma_resid;
+    const bool zero_start = X0 == nullptr;
+    bool fuse_convert = !mfma_resid && !zero_start;
     if (const char* env = getenv("JACOBI_REFINE_FUSED_CONVERT"))
         fuse_convert = fuse_convert && strcmp(env, "0") != 0;
     if (!fuse_convert) {
@@ -123,6 +125,16 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     // One residual pass: x <- x + d, r = B - A x, ||r||_2 / ||B||_2.  Leaves
     // the outcome (STOP_*) in *stop and the relative residual in rel.
     auto residual_pass = [&](uint32_t* stop) -> jacobi_status {
+        if (zero_start && outer == 0) {
+            // r = B - A 0 = B exactly; x stays 0; ||r|| / ||B|| = 1 (or 0 for B = 0,
+            // where x = 0 solves the system)
+            HIP_TRY(launch_rhs_residual((const double*)B, ldb, n, (int)k, kp,
+                                        (double*)c->r64.p, (float*)c->rlo.p, s));
+            HIP_TRY(launch_copy_rows(8, xcur, kp, xnext, kp, n, (int)k, s));
+            *stop = bnorm == 0.0 ? STOP_CONVERGED : STOP_RUNNING;
+            rel = bnorm == 0.0 ? 0.0 : 1.0;
+            return JACOBI_OK;
+        }
         if (mfma_resid) {
             ResidItem it{};
             it.n = n;

@@ -137,23 +137,48 @@ def test_c4_full_size(jac):
 @pytest.mark.parametrize("lo", ["bf16", "f32"])
 @pytest.mark.parametrize("n,pad", [(2, 0), (37, 1), (1024, 0), (1031, 1), (9000, 0)])
 def test_fused_conversion_bitwise(jac, monkeypatch, lo, n, pad):
-    """With one right-hand side the first residual pass writes A_lo while it
-    streams A.  The reduced copy equals the conversion kernel's bitwise, so the
-    whole refinement (X, counts, residual) is bitwise the same as with a
-    separate conversion pass; odd leading dimensions take the unaligned
-    (element) path, n = 9000 several staged x chunks."""
+    """From a given x0 with one right-hand side, the first residual pass
+    writes A_lo while it streams A: the reduced copy equals the conversion
+    kernel's bitwise, so the whole refinement (X, counts, residual) is bitwise
+    the same as with a separate conversion pass.  From x0 = 0 the first
+    residual is B itself (no pass over A): bitwise the same as passing an
+    explicit zero x0.  Odd leading dimensions take the unaligned (element)
+    path, n = 9000 several staged x chunks."""
     import torch
     A, _, B = synth.dominant(n, 1, 4100 + n + pad, synth.MULTIPLICATIVE, 0.5, 1.0)
     Ad = _padded(A, pad)
     Bd = dev(B)
+    x0 = dev(np.random.default_rng(n).uniform(-1, 1, size=(n, 1)))
     out = {}
     for fused in ("0", "1"):
         monkeypatch.setenv("JACOBI_REFINE_FUSED_CONVERT", fused)
         say("fused conversion", lo, n, pad, fused)
-        out[fused] = jac.solve(Ad, Bd, mode="refine", sweep_dtype=lo)
+        out[fused] = jac.solve(Ad, Bd, x0, mode="refine", sweep_dtype=lo)
     monkeypatch.delenv("JACOBI_REFINE_FUSED_CONVERT")
-    (X0, i0), (X1, i1) = out["0"], out["1"]
-    assert i1["status"] == jac.OK, i1
-    for key in ("status", "iterations", "outer_iterations", "rel_residual", "final_delta"):
-        assert i0[key] == i1[key], (key, i0, i1)
-    assert torch.equal(X0, X1)
+    say("zero start", lo, n, pad)
+    out["none"] = jac.solve(Ad, Bd, mode="refine", sweep_dtype=lo)
+    out["zeros"] = jac.solve(Ad, Bd, torch.zeros_like(Bd), mode="refine", sweep_dtype=lo)
+    for a, b in (("0", "1"), ("none", "zeros")):
+        (X0, i0), (X1, i1) = out[a], out[b]
+        assert i1["status"] == jac.OK, (b, i1)
+        for key in ("status", "iterations", "outer_iterations", "rel_residual", "final_delta"):
+            assert i0[key] == i1[key], (a, b, key, i0, i1)
+        assert torch.equal(X0, X1), (a, b)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_zero_start_edges(jac, k):
+    """From x0 = 0 the first residual is B: B = 0 is solved at once by x = 0
+    (relative residual 0, no inner sweep); with max_outer = 0 the call
+    returns x = 0 with relative residual 1."""
+    import torch
+    A, _, B = synth.dominant(300, k, 4200 + k, synth.MULTIPLICATIVE, 0.5, 1.0)
+    say("zero start edges", k)
+    X, info = jac.solve(dev(A), dev(np.zeros_like(B)), mode="refine")
+    assert info["status"] == jac.OK and info["outer_iterations"] == 1
+    assert info["iterations"] == 0 and info["rel_residual"] == 0.0
+    assert not bool(torch.any(X != 0))
+    X, info = jac.solve(dev(A), dev(B), mode="refine", max_outer=0)
+    assert info["status"] == jac.NOT_CONVERGED and info["outer_iterations"] == 1
+    assert info["rel_residual"] == 1.0
+    assert not bool(torch.any(X != 0))
