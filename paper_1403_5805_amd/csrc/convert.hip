@@ -44,14 +44,16 @@ __global__ void k_convert(const double* __restrict__ A, int64_t lda, int64_t n,
                     if constexpr (sizeof(TO) == 4) {
                         const f32x4 w = {narrow<TO>(v[u][0].x), narrow<TO>(v[u][0].y),
                                          narrow<TO>(v[u][1].x), narrow<TO>(v[u][1].y)};
-                        *reinterpret_cast<f32x4*>(o + j) = w;
+                        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(o + j));
                     } else {
                         // element j in the low half of the first word (little endian)
                         const uint32_t lo = (uint32_t)narrow<TO>(v[u][0].x) |
                                             ((uint32_t)narrow<TO>(v[u][0].y) << 16);
                         const uint32_t hi = (uint32_t)narrow<TO>(v[u][1].x) |
                                             ((uint32_t)narrow<TO>(v[u][1].y) << 16);
-                        *reinterpret_cast<uint2*>(o + j) = make_uint2(lo, hi);
+                        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+                        const u32x2 w = {lo, hi};
+                        __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(o + j));
                     }
                 }
             }
