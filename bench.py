@@ -111,7 +111,7 @@ def main() -> int:
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the row-block sharding across GPUs is described in DESIGN.md, not built)",
+              "(the row-block sharding across GPUs is a design note, not built)",
               file=sys.stderr)
         return 2
 
