@@ -110,7 +110,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: the solver runs on one GPU; multi-GPU runs are not supported "
               "(the row-block sharding across GPUs is a design note, not built)",
               file=sys.stderr)
         return 2
