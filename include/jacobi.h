@@ -168,12 +168,15 @@ typedef struct {
 
 /* Solve `count` independent systems (sec. 2 iteration on each) with one
  * persistent launch.  a_dtype F32 or BF16: A as given, B/X0/X float, every
- * system k <= 32; the sweeps run on MFMA tiles, large systems are split over
- * several workgroups that meet at a per-system device barrier after each
- * sweep, small systems are owned by one workgroup and packed.  Every system
- * stops on its own (opt->tol / opt->max_iter, PLAIN mode only, INF or L2
- * distance over its n*k entries).  a_dtype F64 runs the systems one after the
- * other through the plain path.
+ * system k <= 32; the sweeps run on MFMA tiles in rounds: round r is sweep r
+ * of every system still running, its rows dealt out to all workgroups as work
+ * items, one device-wide barrier per round (the earlier schedule, with split
+ * systems meeting at per-system barriers and small systems taken whole from a
+ * queue, is selected by the environment variable JACOBI_BATCHED_SCHED=planned;
+ * both give bitwise the same X).  Every system stops on its own (opt->tol /
+ * opt->max_iter, PLAIN mode only, INF or L2 distance over its n*k entries) and
+ * leaves the rounds.  a_dtype F64 runs the systems one after the other through
+ * the plain path.
  *
  * systems, infos: host arrays of `count` entries.  Returns JACOBI_OK when the
  * launch ran (per-system outcomes in infos[i].status; a system with bad
