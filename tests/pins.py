@@ -351,7 +351,79 @@ def pin_update_and_residual(lib):
     assert np.allclose(R, B - A @ X, rtol=1e-12, atol=1e-12)
 
 
+def _int_system(rng, n, k, diag_extra=True):
+    """Integer matrix (entries -9..9, non-symmetric, a_ii = rowsum + 1..4) and
+    integer right-hand sides: every product and partial sum the residual or a
+    single update forms is an integer far below 2^53, hence exact in binary64
+    in any order."""
+    A = rng.integers(-9, 10, size=(n, n)).astype(np.int64)
+    np.fill_diagonal(A, 0)
+    if diag_extra:
+        np.fill_diagonal(A, np.abs(A).sum(axis=1) + rng.integers(1, 5, size=n))
+    return A
+
+
+def pin_residual_exact(lib):
+    """R = B - A X (the residual the refinement tests against; the plain
+    definition).  Pinned without the oracle's own formula: (1) on a planted
+    integer system B = A X_true (formed in int64) R is exactly zero; (2) at
+    X_true + E with integer E, R = -A E exactly (int64 product: a transposed
+    A, a dropped diagonal term or a sign error changes it); (3) at the
+    hand-worked 3x3 iterates (dyadic rationals) R equals the exact rational
+    residual bitwise."""
+    rng = np.random.default_rng(71)
+    for n, k in ((1, 1), (6, 3), (29, 2), (64, 5)):
+        A = _int_system(rng, n, k)
+        Xt = rng.integers(-4, 5, size=(n, k)).astype(np.int64)
+        B = A @ Xt
+        R = oracle.residual(A.astype(float), B.astype(float), Xt.astype(float), lib=lib)
+        assert np.array_equal(R, np.zeros((n, k))), (n, k)
+        E = rng.integers(-3, 4, size=(n, k)).astype(np.int64)
+        R = oracle.residual(A.astype(float), B.astype(float), (Xt + E).astype(float), lib=lib)
+        assert np.array_equal(R, (-(A @ E)).astype(float)), (n, k)
+    Af, b, _, rows = read_golden("hand_3x3.txt")
+    for _, vals in rows:
+        want = [b[i] - sum(Af[i][j] * vals[j] for j in range(3)) for i in range(3)]
+        R = oracle.residual(_f(Af), np.array([float(v) for v in b]),
+                            np.array([float(v) for v in vals]), lib=lib)
+        assert [Fraction(v) for v in R] == want, (R, want)
+
+
+def pin_update_rows_exact(lib):
+    """One component update at chosen rows (component equation of sec. 2),
+    for A in binary64 and in binary32 (the promoted FP32 system).  On integer
+    inputs the sum is exact, so the result is the correctly rounded quotient
+    (b_i - sum_{j != i} a_ij x_j) / a_ii, which Python's integer true division
+    gives exactly; and on random inputs it equals bitwise the row of one sweep
+    of the pinned driver (tol = 0, L = 1) started from the same iterate."""
+    rng = np.random.default_rng(72)
+    for n, k in ((1, 1), (5, 2), (40, 3)):
+        A = _int_system(rng, n, k)
+        B = rng.integers(-50, 51, size=(n, k)).astype(np.int64)
+        X = rng.integers(-7, 8, size=(n, k)).astype(np.int64)
+        rows = np.unique(rng.integers(0, n, size=min(n, 6)))
+        want = np.empty((rows.size, k))
+        for r, i in enumerate(rows):
+            for c in range(k):
+                s = sum(int(A[i, j]) * int(X[j, c]) for j in range(n) if j != i)
+                want[r, c] = (int(B[i, c]) - s) / int(A[i, i])
+        for Aform in (A.astype(np.float64), A.astype(np.float32)):
+            got = oracle.update_rows(Aform, B.astype(float), X.astype(float), rows, lib=lib)
+            assert np.array_equal(got, want), (n, k, Aform.dtype)
+    for n, k in ((17, 1), (96, 4)):
+        A32, _, B32 = synth.dominant_f32(n, k, 900 + n)
+        A64, B64 = A32.astype(np.float64), B32.astype(np.float64)
+        X0 = rng.uniform(-1, 1, size=(n, k))
+        x1, info = oracle.jacobi(A64, B64, X0=X0, tol=0.0, max_iter=1, lib=lib)
+        assert info["iterations"] == 1
+        rows = np.arange(n)
+        for Aform in (A64, A32):
+            got = oracle.update_rows(Aform, B64, X0, rows, lib=lib)
+            assert np.array_equal(got, x1.reshape(n, k)), (n, k, Aform.dtype)
+
+
 PINS = [pin_hand_2x2, pin_hand_3x3, pin_brute_force_tiny, pin_lapack_solution,
         pin_fixed_point_and_contraction, pin_closed_form_family, pin_special_cases,
         pin_tol_zero_and_cap, pin_scaling_invariance, pin_column_independence, pin_resume,
-        pin_failures, pin_norms, pin_planted_solution, pin_update_and_residual]
+        pin_failures, pin_norms, pin_planted_solution, pin_update_and_residual,
+        pin_residual_exact, pin_update_rows_exact]

@@ -83,6 +83,26 @@ MUTANTS = [
     ("zero diagonal unchecked", "if (d == 0.0) { *bad = i; return ORACLE_ERR_ZERO_DIAGONAL; }",
      ""),
     ("l2 without sqrt", "return norm == ORACLE_NORM_L2 ? sqrt(acc) : acc;", "return acc;"),
+    # the residual R = B - A X used by the refinement checks
+    ("residual sign", "R[i * ldr + c] = B[i * ldb + c] - s;", "R[i * ldr + c] = s - B[i * ldb + c];"),
+    ("residual drops the diagonal term",
+     "                double p = A[i * lda + j] * X[j * ldx + c];",
+     "                if (j == i) continue;\n                double p = A[i * lda + j] * X[j * ldx + c];"),
+    ("residual transposed A", "double p = A[i * lda + j] * X[j * ldx + c];",
+     "double p = A[j * lda + i] * X[j * ldx + c];"),
+    ("residual reads column 0 only", "double p = A[i * lda + j] * X[j * ldx + c];",
+     "double p = A[i * lda + j] * X[j * ldx];"),
+    # single-row updates (binary64 and the promoted binary32 matrix)
+    ("row update of the wrong row",
+     "oracle_component(n, k, A, lda, B, ldb, Xold, ldo, rows[r], c);",
+     "oracle_component(n, k, A, lda, B, ldb, Xold, ldo, r, c);"),
+    ("f32 row update keeps the diagonal",
+     "                if (j == i) continue;\n                double p = (double)row[j]",
+     "                double p = (double)row[j]"),
+    ("f32 row update b sign", "out[r * k + c] = (B[i * ldb + c] - s) / (double)row[i];",
+     "out[r * k + c] = (-B[i * ldb + c] - s) / (double)row[i];"),
+    ("f32 row update transposed A", "double p = (double)row[j] * Xold[j * ldo + c];",
+     "double p = (double)A[j * lda + i] * Xold[j * ldo + c];"),
 ]
 
 
