@@ -264,6 +264,16 @@ JACOBI_API jacobi_status jacobi_serve_stats_get(jacobi_server* srv, jacobi_serve
  * untouched).  Frees every device buffer of the server. */
 JACOBI_API jacobi_status jacobi_serve_destroy(jacobi_server* srv);
 
+/* Release the per-device default contexts (the ctx = NULL workspaces: device
+ * buffers, pinned staging memory, events), after waiting for the device.
+ * Meant for process teardown, before the HIP runtime shuts down (the Python
+ * binding calls it from an interpreter exit hook, after closing its servers
+ * and contexts).  Contexts made by jacobi_ctx_create and servers are not
+ * touched: destroy them first.  Must not run concurrently with a call that
+ * uses a default context.  A later call with ctx = NULL creates a new default
+ * context.  Returns JACOBI_OK. */
+JACOBI_API jacobi_status jacobi_shutdown(void);
+
 /* Human-readable name of a status code (static string). */
 JACOBI_API const char* jacobi_status_string(int32_t status);
 

@@ -132,6 +132,7 @@ class Context:
         if st != OK:
             raise RuntimeError(f"jacobi_ctx_create: {status_string(st)} {last_error()}")
         self.handle = h
+        _lib.track(self)
 
     def close(self):
         if self.handle:

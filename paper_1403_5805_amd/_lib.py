@@ -5,8 +5,10 @@ kernels.  Loading fails loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjacobi.so")
@@ -184,5 +186,30 @@ def load():
         lib.jacobi_serve_stats_get.argtypes = [vp, ctypes.POINTER(ServeStats)]
         lib.jacobi_serve_destroy.restype = i32
         lib.jacobi_serve_destroy.argtypes = [vp]
+    lib.jacobi_shutdown.restype = i32
+    lib.jacobi_shutdown.argtypes = []
     _lib = lib
+    atexit.register(_shutdown)
     return lib
+
+
+# Servers and contexts still open at interpreter exit.  They are closed, and
+# the library's default contexts released, by an exit hook that runs before
+# the HIP runtime is torn down (Python's exit hooks run before the C
+# library's), so no device memory, event or worker thread outlives it.
+_open_handles: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def track(obj) -> None:
+    """Register an object with a close() method for the exit hook."""
+    _open_handles.add(obj)
+
+
+def _shutdown() -> None:
+    for obj in list(_open_handles):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        _lib.jacobi_shutdown()

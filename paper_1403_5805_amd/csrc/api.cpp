@@ -118,8 +118,8 @@ void ctx_release(jacobi_ctx* c) {
     c->prof_ev.clear();
 }
 
-static std::mutex g_default_mu;
-static std::vector<jacobi_ctx*> g_default_ctx;
+std::mutex g_default_mu;
+std::vector<jacobi_ctx*> g_default_ctx;
 
 jacobi_ctx* default_ctx(jacobi_status* st) {
     int dev = 0;
@@ -499,5 +499,28 @@ const char* jacobi_status_string(int32_t s) {
 }
 
 const char* jacobi_last_error(void) { return jac::g_last_error.c_str(); }
+
+jacobi_status jacobi_shutdown(void) {
+    try {
+        std::vector<jacobi_ctx*> all;
+        {
+            std::lock_guard<std::mutex> g(jac::g_default_mu);
+            all.swap(jac::g_default_ctx);
+        }
+        for (jacobi_ctx* c : all) {
+            if (!c) continue;
+            {
+                std::lock_guard<std::mutex> g(c->mu);
+                hipSetDevice(c->device);
+                hipDeviceSynchronize();
+                ctx_release(c);
+            }
+            delete c;
+        }
+        return JACOBI_OK;
+    } catch (...) {
+        return JACOBI_ERR_INTERNAL;
+    }
+}
 
 }  // extern "C"

@@ -20,9 +20,13 @@
 //     maximum, reduced across the grid with one atomic max per workgroup on
 //     the bit pattern of the non-negative double (a NaN compares above +Inf,
 //     so a NaN distance is never lost).
-//   * The last workgroup to finish (atomic ticket) takes the stop decision and
-//     writes a device stop flag; later sweep launches see it and return at once,
-//     so the host only checks the flag every few sweeps.
+//   * Stop decision without a grid-wide wait: sweep launch `seq` publishes its
+//     distance atomics into reduction slot seq % 3 and ends.  Every workgroup
+//     of the next launch reads that slot as it starts and takes the same stop
+//     decision (workgroup 0 records it, with the device stop flag, and clears
+//     slot (seq + 1) % 3 for the launch after); the last launch of a host group
+//     is decided by a one-workgroup decide kernel.  Launches queued after a
+//     stop return at once, so the host only reads the flag every few sweeps.
 //   * The same kernel, in residual mode, computes r = b - A x in FP64 (no
 //     diagonal mask, no division) for iterative refinement, with the update
 //     x += d fused into the staging of x.
@@ -928,9 +932,10 @@ LaunchCfg default_cfg(int32_t a_dtype, int64_t n, int32_t k, int num_cus) {
         }
     }
     // At least four rows per workgroup: below that a small system's sweep is
-    // a latency chain (staging, two rows, the distance atomics and the
-    // deciding workgroup's ticket) that more workgroups only lengthen
-    // (n = 512 FP64: 19.6 us per sweep with 128 workgroups, 24.4 with 256).
+    // a latency chain (the decision read, staging, a few rows and the distance
+    // atomics) that more workgroups only lengthen (n = 512 FP64, measured with
+    // an earlier last-workgroup decision: 19.6 us per sweep with 128
+    // workgroups, 24.4 with 256).
     g = std::max<int64_t>(1, std::min<int64_t>(g, (n + 3) / 4));
     c.rows_per_wg = (n + g - 1) / g;
     c.grid = (int)((n + c.rows_per_wg - 1) / c.rows_per_wg);

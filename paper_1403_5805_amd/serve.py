@@ -40,6 +40,7 @@ class Server:
         self.handle = h
         self._keep = {}
         self._mu = threading.Lock()
+        _lib.track(self)
 
     def submit(self, A: np.ndarray, B: np.ndarray, out: np.ndarray | None = None,
                sweep_dtype: str = "bf16", rel_tol: float = 1e-12):

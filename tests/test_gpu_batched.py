@@ -231,7 +231,9 @@ def test_c3_full_size_properties(jac):
     """The full batched workload (256 systems, n log-uniform in [256, 4096],
     k = 32): every system converges and satisfies the fixed-point property
     ||x - D^-1 (b - (A - D) x)||_inf <= 2 * Delta_final + O(u) (checked in FP64
-    with torch on the device); two systems are compared with the oracle."""
+    with torch on the device); every 8th system, the smallest and the largest
+    are compared with the oracle (count within one sweep, X at the FP32 bar).
+    The oracle runs in threads (its C calls release the interpreter lock)."""
     import torch
     ns = synth.c3_sizes()
     sysl = []
@@ -247,11 +249,19 @@ def test_c3_full_size_properties(jac):
         fp = (B64 - (A64 @ X64 - d[:, None] * X64)) / d[:, None]
         gap = (X64 - fp).abs().max().item()
         assert gap <= 2 * info["final_delta"] + 1e-5 * X64.abs().max().item()
-    for i in (int(np.argmin(ns)), int(np.argmax(ns))):
+    picks = sorted(set(range(0, len(ns), 8)) | {int(np.argmin(ns)), int(np.argmax(ns))})
+
+    def ref(i):
         A32, _, B32 = synth.c3_system(i, int(ns[i]))
-        xo, io = _oracle32(A32, B32, 1e-6, 1000)
-        assert abs(infos[i]["iterations"] - io["iterations"]) <= 1
-        assert rel_err(host(xs[i]), xo) <= REL_F32
+        return _oracle32(A32, B32, 1e-6, 1000)
+
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        refs = dict(zip(picks, ex.map(ref, picks)))
+    for i in picks:
+        xo, io = refs[i]
+        assert abs(infos[i]["iterations"] - io["iterations"]) <= 1, (i, infos[i], io)
+        assert rel_err(host(xs[i]), xo) <= REL_F32, i
 
 
 def test_strided_out_with_x0(jac):

@@ -182,3 +182,106 @@ def test_zero_start_edges(jac, k):
     assert info["status"] == jac.NOT_CONVERGED and info["outer_iterations"] == 1
     assert info["rel_residual"] == 1.0
     assert not bool(torch.any(X != 0))
+
+
+def _rounding_system(n, fmt, seed):
+    """FP64 system whose entries sit on, just inside and exactly at the
+    rounding points of the reduced format (bf16: 8 significant bits, f32: 24),
+    built so that two FP32-accumulated sweeps on the correctly rounded copy
+    are exact.
+
+    * diagonal: +-2^t (t in 2..4) plus an offset of half a unit above (a tie,
+      rounds down to the even 2^t), a quarter unit below (the tie between 2^t
+      and the value below, whose spacing is half as wide), or just inside
+      either tie; a few rows use a diagonal near 2^-130 (subnormal in both
+      formats) with a tie offset and b = 2^-120, so that d = 2^10;
+    * b: small integers, so d^(1) = b / 2^t has at most four significant bits;
+    * off-diagonals of the rows with b != 0: a few short values (v in
+      {0.375, 0.625, 0.75, 0.875, 1.25, 1.5}, either sign) on or inside a tie
+      of v, all of which round to v; every product and partial sum of the
+      second sweep is then exact in FP32 in any order;
+    * rows with b = 0 (d = 0 in both sweeps) only meet columns of other such
+      rows; their columns carry values that matter only for the rounding
+      itself: long random values, subnormal-range values and values just below
+      the overflow threshold (rounded to the largest finite value, never to
+      inf, which times d = 0 would give NaN).
+    Returns (A, b) with A in FP64."""
+    p = 8 if fmt == "bf16" else 24
+    rng = np.random.default_rng(seed)
+    ulp = lambda v: 2.0 ** (np.floor(np.log2(abs(v))) - (p - 1))  # noqa: E731
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    kind = rng.choice(3, size=n, p=[0.2, 0.7, 0.1])  # 0: b = 0, 1: ordinary, 2: subnormal diag
+    kind[0], kind[1], kind[2] = 0, 1, 2
+    zero = np.flatnonzero(kind == 0)
+    live = np.flatnonzero(kind == 1)
+    inside = 0.5 - 2.0 ** -12
+    for i in range(n):
+        sgn = rng.choice([-1.0, 1.0])
+        if kind[i] == 2:
+            v = 2.0 ** -130
+            q = 2.0 ** (-133 if fmt == "bf16" else -149)
+            A[i, i] = sgn * (v + rng.choice([0.5, -0.5, inside, -inside, 0.0]) * q)
+            b[i] = sgn * 2.0 ** -120
+            continue
+        v = 2.0 ** rng.integers(2, 5)
+        u = ulp(v)
+        A[i, i] = sgn * (v + rng.choice([0.5, -0.25, inside * 1.0, -inside / 2, 0.0]) * u)
+        if kind[i] == 0:
+            for j in rng.choice(zero, size=min(4, len(zero)), replace=False):
+                if j != i:
+                    A[i, j] = rng.uniform(-1, 1)
+            continue
+        b[i] = rng.choice([-1.0, 1.0]) * rng.integers(1, 9)
+        for j in rng.choice(live, size=min(5, len(live)), replace=False):
+            if j == i:
+                continue
+            w = rng.choice([0.375, 0.625, 0.75, 0.875, 1.25, 1.5]) * rng.choice([-1.0, 1.0])
+            A[i, j] = w + rng.choice([0.5, -0.5, inside, -inside, 0.25, 0.0]) * ulp(w)
+    # columns of b = 0 rows in ordinary rows: values whose rounding does not
+    # reach the result
+    top = (2.0 - 2.0 ** -(p - 1)) * 2.0 ** 127  # largest finite value of the format
+    for i in live:
+        for j in rng.choice(zero, size=min(3, len(zero)), replace=False):
+            c = rng.integers(3)
+            if c == 0:
+                A[i, j] = rng.uniform(-1, 1)
+            elif c == 1:
+                A[i, j] = rng.choice([-1.0, 1.0]) * (2.0 ** -131 + 2.0 ** -135)
+            else:
+                A[i, j] = rng.choice([-1.0, 1.0]) * (top + 0.25 * 2.0 ** (127 - (p - 1)))
+    return A, b
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f32"])
+@pytest.mark.parametrize("n,k,pad,x0", [(40, 1, 0, None), (203, 1, 1, None), (203, 1, 0, "zero"),
+                                        (129, 1, 1, "zero"), (97, 3, 1, None), (150, 8, 0, None),
+                                        (75, 16, 1, None)])
+def test_reduced_copy_rounding_bitwise(jac, fmt, n, k, pad, x0):
+    """The device's reduced copy A_lo = RNE(A) against the oracle's rounding.
+
+    From x = 0, one correction with two inner sweeps (max_outer = 1,
+    max_inner = 2) returns X = d^(2), the second Jacobi iterate on
+    (A_lo, fl32(B)).  On the system of _rounding_system every step of that
+    iterate is exact in FP32 when A_lo is rounded correctly, so X must equal
+    the oracle's two sweeps on the oracle-rounded copy bitwise.  Covered:
+    the conversion kernel (x0 = None, or k > 1) and the first residual pass
+    that writes A_lo while it streams A (an explicit zero x0 with one column),
+    aligned and odd leading dimensions, the vector sweep (k < 8) and the MFMA
+    sweep (k >= 8)."""
+    A, b = _rounding_system(n, fmt, 4500 + n + k + pad)
+    B = np.repeat(b[:, None], k, axis=1) * (1.0 + (np.arange(k) % 2))[None, :]
+    lo = oracle.round_bf16(A) if fmt == "bf16" else A.astype(np.float32).astype(np.float64)
+    assert np.all(np.isfinite(lo))
+    xe, io = oracle.jacobi(lo, B.astype(np.float32).astype(np.float64), tol=0.0, max_iter=2)
+    assert io["iterations"] == 2
+    Bd = dev(B)
+    xd = None if x0 is None else dev(np.zeros_like(B))
+    say("reduced copy rounding", fmt, n, k, pad, x0)
+    X, info = jac.solve(_padded(A, pad), Bd, xd, mode="refine", sweep_dtype=fmt, max_outer=1,
+                        max_inner=2)
+    assert info["status"] in (jac.OK, jac.NOT_CONVERGED), info
+    assert info["iterations"] == 2 and info["outer_iterations"] == 2, info
+    x = host(X).reshape(n, k)
+    bad = np.flatnonzero((x != np.asarray(xe).reshape(n, k)).any(axis=1))
+    assert bad.size == 0, (fmt, bad[:8], x[bad[:4]], np.asarray(xe).reshape(n, k)[bad[:4]])

@@ -109,3 +109,37 @@ def test_shutdown_with_requests_in_flight(jac):
     xr, _ = oracle.jacobi(A, B, tol=1e-15, max_iter=1000)
     for o in done:
         assert rel_err(o, xr) <= REL_REFINE
+
+
+def test_served_large_requests_match_oracle(jac):
+    """Requests at the large end of the serving mix (n up to 16384, k = 1, 4
+    and 16, FP32 and BF16 inner sweeps), served together with the small mix:
+    large FP64 residual jobs, several arena slabs and inner solves of
+    different sizes in one batched launch.  Each result is compared with the
+    oracle's tight solution x_ref (computed in threads while the server runs)
+    at the refinement bar."""
+    import concurrent.futures as cf
+    shapes = [(16384, 4, "bf16"), (9001, 16, "f32"), (8192, 16, "bf16"), (12289, 1, "f32")]
+    big = []
+    for i, (n, k, lo) in enumerate(shapes):
+        A, Xt, B = synth.dominant(n, k, 7300 + i, synth.MULTIPLICATIVE, 0.2, 1.0)
+        big.append((A, B, lo))
+    reqs = big + _requests()
+    srv = jac.Server(max_active=16)
+    say("serve large", [s[:2] for s in shapes])
+    tickets = [srv.submit(A, B, sweep_dtype=lo)[0] for A, B, lo in reqs]
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        refs = list(ex.map(lambda r: oracle.jacobi(r[0], r[1], tol=1e-15, max_iter=1000)[0],
+                           big))
+    for idx, ((A, B, lo), t) in enumerate(zip(reqs, tickets)):
+        X, info = srv.wait(t, timeout_s=120)
+        assert info["status"] == jac.OK, (idx, info)
+        assert info["rel_residual"] < 1e-12
+        if idx < len(big):
+            err = rel_err(X, refs[idx])
+            print(f"served n={A.shape[0]} k={B.shape[1]} {lo}: err={err:.2e} "
+                  f"outer={info['outer_iterations']} inner={info['iterations']}", flush=True)
+            assert err <= REL_REFINE, (idx, err)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["hbm_in_use"] == 0
+    srv.close()
