@@ -148,7 +148,7 @@ jacobi_ctx* default_ctx(jacobi_status* st) {
     return g_default_ctx[dev];
 }
 
-static int kpad_for(int64_t k) {
+int kpad_for(int64_t k) {
     if (k <= 32) {
         int kt = 1;
         while (kt < k) kt <<= 1;
@@ -218,10 +218,11 @@ static double bits_to_double(uint64_t b) {
 // or `cap` sweeps ran.  bufs[0] holds x^(0); sweep s reads bufs[(s-1)&1] and
 // writes bufs[s&1].  Returns the stop code and the number of sweeps whose
 // result is final (K); the final iterate lives in bufs[K & 1].
-jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const LaunchCfg& cfg,
-                         void* bufs[2], int32_t cap, int32_t sync_every, int profile,
-                         hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
-                         double* xmax_out, double* kernel_ms, int64_t* launches) {
+jacobi_status run_sweeps(const SweepCtl& sc, int32_t a_dtype, SweepArgs args,
+                         const LaunchCfg& cfg, void* bufs[2], int32_t cap, int32_t sync_every,
+                         int profile, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
+                         double* delta_out, double* xmax_out, double* kernel_ms,
+                         int64_t* launches) {
     int32_t done = 0;
     // Launches queued after the device decided to stop return at once (a few
     // microseconds each), so a small system, whose sweeps cost about as much
@@ -230,13 +231,18 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
         (double)args.n * (double)args.lda * (a_dtype == JACOBI_F64 ? 8 : 4);
     int32_t chunk = sync_every > 0 ? sync_every : (sweep_bytes <= 64.0 * 1024 * 1024 ? 16 : 4);
     *stop_out = STOP_RUNNING;
-    if (profile && (int)c->prof_ev.size() < 2 * 512) {
-        while ((int)c->prof_ev.size() < 2 * 512) {
+    if (profile && !sc.prof_ev) {
+        set_error("per-sweep profiling is not available here");
+        return JACOBI_ERR_INVALID_ARG;
+    }
+    if (profile && (int)sc.prof_ev->size() < 2 * 512) {
+        while ((int)sc.prof_ev->size() < 2 * 512) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
-            c->prof_ev.push_back(e);
+            sc.prof_ev->push_back(e);
         }
     }
+    Ctl* const h_ctl = sc.h_ctl;
     const int32_t max_chunk = profile ? 512 : 256;
     while (done < cap) {
         int32_t S = std::min(chunk, cap - done);
@@ -247,21 +253,21 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
             args.seq = sw;
             args.xin = bufs[(sw - 1) & 1];
             args.xout = bufs[sw & 1];
-            if (profile) HIP_TRY(hipEventRecord(c->prof_ev[2 * (q - 1)], s));
+            if (profile) HIP_TRY(hipEventRecord((*sc.prof_ev)[2 * (q - 1)], s));
             HIP_TRY(launch_sweep(a_dtype, args, cfg, s));
-            if (profile) HIP_TRY(hipEventRecord(c->prof_ev[2 * (q - 1) + 1], s));
+            if (profile) HIP_TRY(hipEventRecord((*sc.prof_ev)[2 * (q - 1) + 1], s));
         }
         // each launch decides its predecessor; the group's last one is decided
         // here (a no-op when the phase has already stopped)
         HIP_TRY(launch_decide(args, cfg.grid * ((args.k + 31) / 32), s));
-        HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_ctl, sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const Ctl& h = *c->h_ctl;
+        const Ctl& h = *h_ctl;
         if (profile) {
             const int32_t ran = h.stop != STOP_RUNNING ? std::max(0, h.stop_sweep - done) : S;
             for (int32_t q = 1; q <= ran; ++q) {
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, c->prof_ev[2 * (q - 1)], c->prof_ev[2 * (q - 1) + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, (*sc.prof_ev)[2 * (q - 1)], (*sc.prof_ev)[2 * (q - 1) + 1]));
                 *kernel_ms += ms;
                 *launches += 1;
             }
@@ -277,13 +283,13 @@ jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const L
         if (sync_every == 0) chunk = std::min(chunk * 2, 256);
     }
     if (cap == 0) {
-        HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_ctl, sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (c->h_ctl->stop == STOP_INVALID) *stop_out = STOP_INVALID;
+        if (h_ctl->stop == STOP_INVALID) *stop_out = STOP_INVALID;
         *delta_out = -1.0;
     } else {
-        *delta_out = bits_to_double(c->h_ctl->last_delta_bits);
-        *xmax_out = bits_to_double(c->h_ctl->last_xmax_bits);
+        *delta_out = bits_to_double(h_ctl->last_delta_bits);
+        *xmax_out = bits_to_double(h_ctl->last_xmax_bits);
     }
     *k_out = cap;
     return JACOBI_OK;
@@ -308,45 +314,57 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
     HIP_TRY(c->diag.ensure(sx * n));
     HIP_TRY(c->w0.ensure(sx * n * kp));
     HIP_TRY(c->w1.ensure(sx * n * kp));
-    const LaunchCfg cfg = default_cfg(a_dtype, n, (int)k, c->num_cus);
+    PlainWs w{sweep_ctl(c), c->slots, c->parts, c->diag.p, c->w0.p, c->w1.p,
+              c->ev_begin, c->ev_end, c->num_cus};
+    return solve_plain_vec(w, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, s, info);
+}
+
+jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_dtype,
+                              const void* A, int64_t lda, const void* B, int64_t ldb,
+                              const void* X0, void* X, int64_t ldx, const jacobi_options& o,
+                              hipStream_t s, jacobi_info* info) {
+    const int kp = kpad_for(k);
+    const size_t sx = a_dtype == JACOBI_F64 ? 8 : 4;
+    const LaunchCfg cfg = default_cfg(a_dtype, n, (int)k, w.num_cus);
     if (cfg.grid * ((k + 31) / 32) > kMaxParts) {
         set_error("grid too large");
         return JACOBI_ERR_INVALID_ARG;
     }
-    HIP_TRY(hipEventRecord(c->ev_begin, s));
-    HIP_TRY(launch_init_ctl(c->ctl, c->slots, 1, s));
-    HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, c->diag.p, c->w0.p,
-                         c->w1.p, c->ctl, s));
+    Ctl* const ctl = w.sc.ctl;
+    if (w.ev_begin) HIP_TRY(hipEventRecord(w.ev_begin, s));
+    HIP_TRY(launch_init_ctl(ctl, w.slots, 1, s));
+    HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, w.diag, w.w0, w.w1,
+                         ctl, s));
     SweepArgs a{};
     a.A = A;
     a.lda = lda;
     a.B = B;
     a.ldb = ldb;
-    a.diag = c->diag.p;
+    a.diag = w.diag;
     a.n = n;
     a.k = (int)k;
     a.kpad = kp;
     a.ldin = kp;
     a.ldout = kp;
-    a.ctl = c->ctl;
-    a.slots = c->slots;
-    a.parts = c->parts;
+    a.ctl = ctl;
+    a.slots = w.slots;
+    a.parts = w.parts;
     a.tol = o.tol;
     a.test = TEST_ABS;
     a.norm = o.norm;
     const size_t ea = dtype_bytes(a_dtype);
     a.aligned = (((uintptr_t)A % 16) == 0 && ((size_t)lda * ea) % 16 == 0) ? 1 : 0;
-    void* bufs[2] = {c->w0.p, c->w1.p};
+    void* bufs[2] = {w.w0, w.w1};
     uint32_t stop = 0;
     int32_t K = 0;
     double delta = -1.0, xmax = 0.0, kms = 0.0;
     int64_t launches = 0;
-    jacobi_status st = run_sweeps(c, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every, o.profile,
-                                  s, &stop, &K, &delta, &xmax, &kms, &launches);
+    jacobi_status st = run_sweeps(w.sc, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every,
+                                  o.profile, s, &stop, &K, &delta, &xmax, &kms, &launches);
     if (st != JACOBI_OK) return st;
     info->bad_index = -1;
     if (stop == STOP_INVALID) {
-        jacobi_status vs = validation_status(*c->h_ctl, &info->bad_index);
+        jacobi_status vs = validation_status(*w.sc.h_ctl, &info->bad_index);
         info->status = vs;
         info->iterations = 0;
         info->final_delta = -1.0;
@@ -355,11 +373,16 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
         return vs;
     }
     HIP_TRY(launch_copy_rows((int)sx, bufs[K & 1], kp, X, ldx, n, (int)k, s));
-    HIP_TRY(hipEventRecord(c->ev_end, s));
-    HIP_TRY(hipEventSynchronize(c->ev_end));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->ev_begin, c->ev_end));
-    info->device_ms = ms;
+    if (w.ev_begin && w.ev_end) {
+        HIP_TRY(hipEventRecord(w.ev_end, s));
+        HIP_TRY(hipEventSynchronize(w.ev_end));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, w.ev_begin, w.ev_end));
+        info->device_ms = ms;
+    } else {
+        HIP_TRY(hipStreamSynchronize(s));
+        info->device_ms = -1.0;
+    }
     info->iterations = K;
     info->final_delta = K > 0 ? delta : -1.0;
     info->sweep_kernel_ms = kms;

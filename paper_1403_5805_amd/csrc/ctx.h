@@ -71,10 +71,43 @@ jacobi_ctx* default_ctx(jacobi_status* st);
 jacobi_status check_common(int64_t n, int64_t k, int32_t a_dtype, const void* A, int64_t lda,
                            const void* B, int64_t ldb, const void* X, int64_t ldx,
                            const jacobi_options& o);
-jacobi_status run_sweeps(jacobi_ctx* c, int32_t a_dtype, SweepArgs args, const LaunchCfg& cfg,
-                         void* bufs[2], int32_t cap, int32_t sync_every, int profile,
-                         hipStream_t s, uint32_t* stop_out, int32_t* k_out, double* delta_out,
-                         double* xmax_out, double* kernel_ms, int64_t* launches);
+// Control block of a run of sweeps: the device block, its host mirror and
+// the events of per-sweep profiling (null: profiling unavailable).
+struct SweepCtl {
+    Ctl* ctl;
+    Ctl* h_ctl;
+    std::vector<hipEvent_t>* prof_ev;
+};
+inline SweepCtl sweep_ctl(jacobi_ctx* c) { return SweepCtl{c->ctl, c->h_ctl, &c->prof_ev}; }
+
+jacobi_status run_sweeps(const SweepCtl& sc, int32_t a_dtype, SweepArgs args,
+                         const LaunchCfg& cfg, void* bufs[2], int32_t cap, int32_t sync_every,
+                         int profile, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
+                         double* delta_out, double* xmax_out, double* kernel_ms,
+                         int64_t* launches);
+
+// Workspace of a plain solve on the vector sweep kernel (device pointers
+// except h_ctl): diag holds n elements of the iterate type, w0 and w1 n x kp.
+struct PlainWs {
+    SweepCtl sc;
+    Slot* slots;        // [3]
+    double* parts;      // [3][kMaxParts]
+    void* diag;
+    void* w0;
+    void* w1;
+    hipEvent_t ev_begin, ev_end;  // null: device_ms is not measured (-1)
+    int num_cus;
+};
+
+// Padded column count of the iterate buffers for k right-hand sides.
+int kpad_for(int64_t k);
+
+// Plain Jacobi solve on the vector sweep kernel with the given workspace
+// (no allocation).  Arguments as jacobi_solve; the caller has validated them.
+jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_dtype,
+                              const void* A, int64_t lda, const void* B, int64_t ldb,
+                              const void* X0, void* X, int64_t ldx, const jacobi_options& o,
+                              hipStream_t s, jacobi_info* info);
 
 // One system of a batched FP64 residual pass (device pointers; x, d, xnew,
 // r64 and rlo are n x ldx row-major).  xT is workspace of

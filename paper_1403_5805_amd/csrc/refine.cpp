@@ -241,8 +241,9 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         void* dbufs[2] = {c->d0.p, c->d1.p};
         int32_t K = 0;
         double xmax = 0.0;
-        jacobi_status st = run_sweeps(c, lo, ia, icfg, dbufs, o.max_inner, o.sync_every, o.profile,
-                                      s, stop, &K, &last_delta, &xmax, &kms, &launches);
+        jacobi_status st = run_sweeps(sweep_ctl(c), lo, ia, icfg, dbufs, o.max_inner,
+                                      o.sync_every, o.profile, s, stop, &K, &last_delta, &xmax,
+                                      &kms, &launches);
         if (st != JACOBI_OK) return st;
         inner_total += K;
         *dout = (const float*)dbufs[K & 1];
