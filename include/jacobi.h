@@ -264,6 +264,36 @@ JACOBI_API jacobi_status jacobi_serve_stats_get(jacobi_server* srv, jacobi_serve
  * untouched).  Frees every device buffer of the server. */
 JACOBI_API jacobi_status jacobi_serve_destroy(jacobi_server* srv);
 
+/* Size of the fixed per-device workspace of jacobi_solve_noalloc (bytes). */
+#define JACOBI_NOALLOC_MAX_BYTES (24u << 20)
+
+/* jacobi_solve without any allocation, for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid the allocator).  Same arguments, conventions and results as
+ * jacobi_solve in PLAIN mode on the current HIP device, restricted to the
+ * vector sweep path: k <= 4 right-hand sides, opt->mode = PLAIN,
+ * opt->profile = 0 (other values: JACOBI_ERR_INVALID_ARG).  X, the count and
+ * the distance are bitwise those of jacobi_solve for the same input.
+ *
+ * Workspace: one fixed device array per device (JACOBI_NOALLOC_MAX_BYTES,
+ * allocated with the library's code object and held until the process
+ * ends), which must hold the control block, the reduction slots, 1.5 MiB of
+ * partial sums, the diagonal (n elements) and two iterate buffers (n x kp,
+ * kp = k rounded up to a power of two), each rounded up to 256 bytes, with
+ * 8-byte elements for F64 and 4-byte for F32/BF16; a larger n * k returns
+ * JACOBI_ERR_INVALID_ARG with the sizes in jacobi_last_error() before any
+ * device work (F64, k = 1: n up to about 980000).  Every call on a device
+ * uses that device's one array, and the library serialises such calls with
+ * a per-device lock; work of a call is complete when it returns (it waits on
+ * `stream`), so it cannot be captured into a graph.  Calls that overlap on
+ * one device by other means (another copy of the library in the same
+ * process) would race.  info->device_ms is -1 (no events are created). */
+JACOBI_API jacobi_status jacobi_solve_noalloc(int64_t n, int64_t k, int32_t a_dtype,
+                                              const void* A, int64_t lda, const void* B,
+                                              int64_t ldb, const void* X0, void* X,
+                                              int64_t ldx, const jacobi_options* opt,
+                                              hipStream_t stream, jacobi_info* info);
+
 /* Release the per-device default contexts (the ctx = NULL workspaces: device
  * buffers, pinned staging memory, events), after waiting for the device.
  * Meant for process teardown, before the HIP runtime shuts down (the Python

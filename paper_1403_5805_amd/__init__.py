@@ -20,7 +20,8 @@ from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVA
                    ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
                    F64, NOT_CONVERGED, OK, PENDING, Info, Options)
 
-__all__ = ["solve", "solve_batched", "Batch", "Server", "status_string", "last_error", "Context",
+__all__ = ["solve", "solve_noalloc", "solve_batched", "Batch", "Server", "status_string",
+           "last_error", "Context",
            "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
            "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
            "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
@@ -153,7 +154,7 @@ def _stream_handle(stream, device):
 
 
 def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
-          raise_on_error: bool = False, **opts):
+          raise_on_error: bool = False, _noalloc: bool = False, **opts):
     """Solve A X = B by Jacobi sweeps on the GPU.
 
     A: (n, n) torch tensor on the GPU, float64 / float32 / bfloat16, unit column
@@ -186,13 +187,18 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
     if x0 is not None and not vec and _ld(x0) != _ld(out):
         # X0 is read with out's leading dimension
         x0 = torch.empty((n, _ld(out)), dtype=vdt, device=A.device)[:, :k].copy_(x0)
+    noalloc = _noalloc
     o = make_options(**opts)
     info = Info()
-    st = lib.jacobi_solve(ctx.handle if ctx else None, n, k, dt, _ptr(A), _ld(A),
-                          _ptr(B), _ld(B) if not vec else 1,
-                          _ptr(x0) if x0 is not None else None, _ptr(out),
-                          _ld(out) if not vec else 1, ctypes.byref(o),
-                          _stream_handle(stream, A.device), ctypes.byref(info))
+    args = (n, k, dt, _ptr(A), _ld(A), _ptr(B), _ld(B) if not vec else 1,
+            _ptr(x0) if x0 is not None else None, _ptr(out), _ld(out) if not vec else 1,
+            ctypes.byref(o), _stream_handle(stream, A.device), ctypes.byref(info))
+    if noalloc:
+        if ctx is not None:
+            raise ValueError("the no-allocation entry point takes no context")
+        st = lib.jacobi_solve_noalloc(*args)
+    else:
+        st = lib.jacobi_solve(ctx.handle if ctx else None, *args)
     d = info.as_dict()
     d["status_name"] = status_string(st)
     if st < 0:
@@ -200,6 +206,16 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
         if raise_on_error:
             raise RuntimeError(f"jacobi_solve failed: {d['status_name']}: {d['error']}")
     return out, d
+
+
+def solve_noalloc(A, B, x0=None, *, out=None, stream=None, raise_on_error: bool = False,
+                  **opts):
+    """jacobi_solve_noalloc: the plain solve with its workspace in the
+    library's fixed per-device array (no device allocation by the library;
+    k <= 4, plain mode).  The caller provides `out` to avoid torch allocating
+    the result.  Same arguments and results as solve()."""
+    return solve(A, B, x0, out=out, stream=stream, raise_on_error=raise_on_error,
+                 _noalloc=True, **opts)
 
 
 from .batched import Batch, solve_batched  # noqa: E402

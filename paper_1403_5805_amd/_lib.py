@@ -186,6 +186,9 @@ def load():
         lib.jacobi_serve_stats_get.argtypes = [vp, ctypes.POINTER(ServeStats)]
         lib.jacobi_serve_destroy.restype = i32
         lib.jacobi_serve_destroy.argtypes = [vp]
+    lib.jacobi_solve_noalloc.restype = i32
+    lib.jacobi_solve_noalloc.argtypes = [i64, i64, i32, vp, i64, vp, i64, vp, vp, i64,
+                                         ctypes.POINTER(Options), vp, ctypes.POINTER(Info)]
     lib.jacobi_shutdown.restype = i32
     lib.jacobi_shutdown.argtypes = []
     _lib = lib

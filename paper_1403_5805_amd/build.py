@@ -26,7 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch=
           "-Wno-unused-command-line-argument"]
 
 SOURCES = ["sweep.hip", "batched.hip", "resid.hip", "convert.hip", "api.cpp", "refine.cpp",
-           "batch_api.cpp", "plan.cpp", "resid_api.cpp", "arena.cpp", "serve.cpp"]
+           "batch_api.cpp", "plan.cpp", "resid_api.cpp", "arena.cpp", "serve.cpp",
+           "noalloc.cpp"]
 
 
 def _compile(src: str) -> str:
