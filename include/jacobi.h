@@ -156,7 +156,7 @@ JACOBI_API jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k,
 
 /* One system of a batch (device pointers; same conventions as jacobi_solve). */
 typedef struct {
-    int64_t n, k;       /* size and right-hand sides (batched FP32/BF16: k <= 32)  */
+    int64_t n, k;       /* size and right-hand sides (k <= 32)                     */
     const void* A;      /* n x n, leading dimension lda                            */
     int64_t lda;
     const void* B;      /* n x k, leading dimension ldb                            */
@@ -167,16 +167,17 @@ typedef struct {
 } jacobi_system;
 
 /* Solve `count` independent systems (sec. 2 iteration on each) with one
- * persistent launch.  a_dtype F32 or BF16: A as given, B/X0/X float, every
- * system k <= 32; the sweeps run on MFMA tiles in rounds: round r is sweep r
+ * persistent launch.  a_dtype F64: A, B, X0, X double, FP64 MFMA tiles
+ * (v_mfma_f64_16x16x4f64, FP64 accumulation); F32 or BF16: A as given,
+ * B/X0/X float, FP32 MFMA tiles with FP32 accumulation.  Every system has
+ * k <= 32 (others get JACOBI_ERR_INVALID_ARG).  The sweeps run in rounds: round r is sweep r
  * of every system still running, its rows dealt out to all workgroups as work
  * items, one device-wide barrier per round (the earlier schedule, with split
  * systems meeting at per-system barriers and small systems taken whole from a
  * queue, is selected by the environment variable JACOBI_BATCHED_SCHED=planned;
  * both give bitwise the same X).  Every system stops on its own (opt->tol /
  * opt->max_iter, PLAIN mode only, INF or L2 distance over its n*k entries) and
- * leaves the rounds.  a_dtype F64 runs the systems one after the other through
- * the plain path.
+ * leaves the rounds.
  *
  * systems, infos: host arrays of `count` entries.  Returns JACOBI_OK when the
  * launch ran (per-system outcomes in infos[i].status; a system with bad

@@ -299,9 +299,10 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
                                  const void* A, int64_t lda, const void* B, int64_t ldb,
                                  const void* X0, void* X, int64_t ldx, const jacobi_options& o,
                                  hipStream_t s, jacobi_info* info) {
-    // Several right-hand sides in FP32 / BF16: the sweep is a real dense
-    // contraction, run on MFMA tiles by the persistent kernel.
-    if (a_dtype != JACOBI_F64 && k >= 8 && k <= 32 && o.profile == 0) {
+    // Several right-hand sides: the sweep is a real dense contraction, run
+    // on MFMA tiles (FP32 for FP32/BF16 A, FP64 for FP64 A) by the
+    // persistent kernel.
+    if (k >= 8 && k <= 32 && o.profile == 0) {
         BatchItem it{n, k, A, lda, B, ldb, X0, X, ldx, o.max_iter};
         jacobi_status st = run_batched(c, 1, &it, a_dtype, o, TEST_ABS, 0.0, s, info);
         if (st != JACOBI_OK) return st;

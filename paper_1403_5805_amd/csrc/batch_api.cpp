@@ -100,8 +100,10 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     Plan plan;
     ItemPlan ip;
     int grid = 0;
+    const size_t ea = a_dtype == JACOBI_F64 ? 8 : (a_dtype == JACOBI_F32 ? 4 : 2);
+    const size_t ex = a_dtype == JACOBI_F64 ? 8 : 4;  // iterate element
     if (sched == 1) {
-        ip = make_items(ns, capacity, tpp, a_dtype == JACOBI_F32 ? 4 : 2);
+        ip = make_items(ns, capacity, tpp, (int)ea);
         grid = ip.grid;
     } else {
         int max_split = 1 << 30;
@@ -123,8 +125,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     auto xld_of = [](int64_t n) { return (n + 63) / 64 * 64; };  // a multiple of every block width
     for (int i = 0; i < count; ++i) {
         off[i] = ws;
-        ws += 3 * align(sizeof(float) * xld_of(items[i].n) * kt) +
-              align(sizeof(float) * items[i].n);
+        ws += 3 * align(ex * xld_of(items[i].n) * kt) + align(ex * items[i].n);
     }
     // device metadata: [sys | st | schedule tables (uploaded) | partial sums]
     //   sched 0 tables: jobs | job_off | queue head (16 bytes) + queue
@@ -161,17 +162,17 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         std::memset(&S, 0, sizeof(S));
         S.A = it.A;
         S.lda = it.lda;
-        S.B = (const float*)it.B;
+        S.B = it.B;
         S.ldb = it.ldb;
-        S.X = (float*)it.X;
+        S.X = it.X;
         S.ldx = it.ldx;
-        S.X0 = (const float*)it.X0;
-        const size_t xb = align(sizeof(float) * xld_of(it.n) * kt);
-        S.buf0 = (float*)base;
-        S.buf1 = (float*)(base + xb);
-        S.bT = (float*)(base + 2 * xb);
+        S.X0 = it.X0;
+        const size_t xb = align(ex * xld_of(it.n) * kt);
+        S.buf0 = base;
+        S.buf1 = base + xb;
+        S.bT = base + 2 * xb;
         S.xld = xld_of(it.n);
-        S.diag = (const float*)(base + 3 * xb);
+        S.diag = base + 3 * xb;
         S.n = it.n;
         S.k = (int32_t)it.k;
         if (sched == 1) {
@@ -295,7 +296,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     for (int i = 0; i < count; ++i) {
         kmax = std::max<int>(kmax, (int)items[i].k);
         nmax = std::max(nmax, items[i].n);
-        bytes += (double)items[i].n * (double)items[i].n * (a_dtype == JACOBI_F32 ? 4.0 : 2.0);
+        bytes += (double)items[i].n * (double)items[i].n *
+                 (a_dtype == JACOBI_F64 ? 8.0 : (a_dtype == JACOBI_F32 ? 4.0 : 2.0));
         if (items[i].X0 && items[i].X0 == items[i].X) alias = true;
     }
     const int rule = count * 4 >= c->num_cus ? 0 : 1;
@@ -402,22 +404,13 @@ extern "C" jacobi_status jacobi_solve_batched(jacobi_ctx* ctx, int32_t count,
             const jacobi_system& y = systems[i];
             const bool ok = y.n >= 1 && y.k >= 1 && y.lda >= y.n && y.ldb >= y.k &&
                             y.ldx >= y.k && y.A && y.B && y.X && y.n <= (int64_t)INT32_MAX &&
-                            (a_dtype == JACOBI_F64 || y.k <= 32);
+                            y.k <= 32;
             if (!ok) continue;
             BatchItem it{y.n, y.k, y.A, y.lda, y.B, y.ldb, y.X0, y.X, y.ldx, o.max_iter};
             items.push_back(it);
             idx.push_back(i);
         }
         if (items.empty()) return JACOBI_OK;
-        if (a_dtype == JACOBI_F64) {
-            // FP64 systems: the plain per-system path, one solve after another.
-            for (size_t q = 0; q < items.size(); ++q) {
-                const BatchItem& it = items[q];
-                solve_plain_locked(c, it.n, it.k, a_dtype, it.A, it.lda, it.B, it.ldb, it.X0, it.X,
-                                   it.ldx, o, stream, &infos[idx[q]]);
-            }
-            return JACOBI_OK;
-        }
         std::vector<jacobi_info> out(items.size());
         st = run_batched(c, (int32_t)items.size(), items.data(), a_dtype, o, TEST_ABS, 0.0,
                          stream, out.data());

@@ -38,6 +38,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace jac {
@@ -45,6 +47,19 @@ namespace jac {
 typedef uint16_t bf16_t;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Iterate type of a launch: FP64 for FP64 A, FP32 (FP32 accumulation) for
+// FP32 and BF16 A.
+template <typename TA>
+struct IterOf {
+    using T = float;
+};
+template <>
+struct IterOf<double> {
+    using T = double;
+};
 
 namespace {
 
@@ -87,7 +102,7 @@ __device__ __forceinline__ void unpack<bf16_t>(const u32x4& v, float* a) {
 }
 
 template <typename TA>
-__device__ __forceinline__ float widen1(TA a);
+__device__ __forceinline__ typename IterOf<TA>::T widen1(TA a);
 template <>
 __device__ __forceinline__ float widen1<float>(float a) {
     return a;
@@ -95,6 +110,10 @@ __device__ __forceinline__ float widen1<float>(float a) {
 template <>
 __device__ __forceinline__ float widen1<bf16_t>(bf16_t a) {
     return bf_to_f(a);
+}
+template <>
+__device__ __forceinline__ double widen1<double>(double a) {
+    return a;
 }
 
 __device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
@@ -124,38 +143,44 @@ __device__ __forceinline__ uint64_t wmax(uint64_t v) {
 // and clear buf1, padding included.  grid = (row blocks, systems).
 template <typename TA>
 __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict__ st, int kt) {
+    using TX = typename IterOf<TA>::T;
     const BSys S = sys[blockIdx.y];
     BState* T = &st[blockIdx.y];
     const TA* A = reinterpret_cast<const TA*>(S.A);
-    float* diag = const_cast<float*>(S.diag);
+    TX* diag = (TX*)const_cast<void*>(S.diag);
+    TX* buf0 = (TX*)S.buf0;
+    TX* buf1 = (TX*)S.buf1;
+    TX* bT = (TX*)S.bT;
+    const TX* X0 = (const TX*)S.X0;
+    const TX* B = (const TX*)S.B;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.xld; i += stride) {
         if (i >= S.n) {
             for (int c = 0; c < kt; ++c) {
-                S.buf0[c * S.xld + i] = 0.0f;
-                S.buf1[c * S.xld + i] = 0.0f;
-                S.bT[c * S.xld + i] = 0.0f;
+                buf0[c * S.xld + i] = TX(0);
+                buf1[c * S.xld + i] = TX(0);
+                bT[c * S.xld + i] = TX(0);
             }
             continue;
         }
-        const float d = widen1<TA>(A[i * S.lda + i]);
+        const TX d = widen1<TA>(A[i * S.lda + i]);
         diag[i] = d;
-        if (d == 0.0f)
+        if (d == TX(0))
             __hip_atomic_fetch_min(&T->bad_diag, 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else if (!isfinite(d))
             __hip_atomic_fetch_min(&T->bad_diag, 2 * i + 1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         bool bad = false;
         for (int c = 0; c < kt; ++c) {
-            float x0 = 0.0f, b = 0.0f;
+            TX x0 = TX(0), b = TX(0);
             if (c < S.k) {
-                if (S.X0) x0 = S.X0[i * S.ldx + c];
-                b = S.B[i * S.ldb + c];
+                if (X0) x0 = X0[i * S.ldx + c];
+                b = B[i * S.ldb + c];
                 if (!isfinite(b) || !isfinite(x0)) bad = true;
             }
-            S.buf0[c * S.xld + i] = x0;
-            S.buf1[c * S.xld + i] = 0.0f;
-            S.bT[c * S.xld + i] = b;
+            buf0[c * S.xld + i] = x0;
+            buf1[c * S.xld + i] = TX(0);
+            bT[c * S.xld + i] = b;
         }
         if (bad)
             __hip_atomic_fetch_min(&T->bad_rhs, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -382,8 +407,8 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
             const int64_t is = ok ? i : r0;  // a row and column that exist
             const int cs = ok ? c : 0;
             e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
-            e_b[u] = *gbl(S.bT + (int64_t)cs * xld + is);
-            e_d[u] = *gbl(S.diag + is);
+            e_b[u] = *gbl((const float*)S.bT + (int64_t)cs * xld + is);
+            e_d[u] = *gbl((const float*)S.diag + is);
         }
         __syncthreads();
 #pragma unroll
@@ -417,6 +442,225 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 }
 
 // ---------------------------------------------------------------------------
+// The FP64 row sweep: sweep_rows with FP64 A, iterate and accumulation, on
+// v_mfma_f64_16x16x4f64.  A block is 16 columns (128 bytes of a row): lane
+// l loads row (l % 16) of a tile with two 16-byte loads, load j of lane group
+// g = l / 16 holding columns 8 j + 2 g + {0, 1}, so each load covers 64
+// contiguous bytes of every row and the two loads the whole line.  Element e
+// of a lane (load e / 2, half e % 2) is MFMA k-step e of the block; the B
+// operand of the same k-steps is two 16-byte loads of the transposed iterate.
+// The output tile puts element (i, j) in lane 16 (i % 4) + j, register i / 4.
+template <int KT, int W, int TPW, int U>
+__device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_t r1,
+                                               const double* xin, double* xout, double* red,
+                                               int tid, int wave, uint64_t& dmax,
+                                               uint64_t& xmax, double& sq) {
+    constexpr int BW = 16;       // columns of one A block
+    constexpr int NT = KT / 16;  // 16-column output tiles
+    const int lane = tid & 63, grp = lane >> 4, li = lane & 15;
+    const double* A = reinterpret_cast<const double*>(S.A);
+    const int64_t n = S.n;
+    const int64_t xld = S.xld;
+    const int k = S.k;
+    const int64_t nb = (n + BW - 1) / BW;  // A blocks per row
+    const int64_t nbf = n / BW;            // blocks entirely inside the row
+    const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
+    const int64_t nfull = (ntw / U) * U;
+    gptr<double> xrow[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) xrow[t] = gbl(xin + (int64_t)(t * 16 + li) * xld + 2 * grp);
+    auto rows_of = [&](gptr<double> (&rows)[TPW], int64_t pr) {
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            int64_t ri = pr + 16 * q + li;
+            if (ri >= r1) ri = r1 - 1;
+            rows[q] = gbl(A + ri * S.lda + 2 * grp);
+        }
+    };
+    auto load_b = [&](f64x2 (&bx)[NT][2], int64_t b) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bx[t][j] = *(gptr<f64x2>)(xrow[t] + b * BW + 8 * j);
+    };
+    auto issue = [&](const gptr<double> (&rows)[TPW], f64x2 (&v)[U][TPW][2],
+                     f64x2 (&bx)[U][NT][2], int64_t t0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t b = wave + W * (t0 + u);
+#pragma unroll
+            for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    v[u][q][j] = __builtin_nontemporal_load(
+                        (gptr<f64x2>)(rows[q] + b * BW + 8 * j));
+            load_b(bx[u], b);
+        }
+    };
+    f64x2 v0[U][TPW][2];
+    f64x2 b0[U][NT][2];
+    bool preloaded = false;
+    gptr<double> arow[TPW];
+    rows_of(arow, r0);
+    for (int64_t pr = r0; pr < r1; pr += 16 * TPW) {
+        int64_t rt[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) rt[q] = pr + 16 * q;
+        f64x4 acc[TPW][NT];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[q][t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        // MFMAs of one block; tile q's diagonal lies in block rt[q] / 16,
+        // at block column li, held by lane group (li % 8) / 2 as element
+        // 2 (li / 8) + li % 2.
+        auto mfma_block = [&](f64x2 (&a)[TPW][2], const f64x2 (&bx)[NT][2], int64_t b) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                if (b == rt[q] / BW) {
+                    const int dpos = ((li & 7) >> 1) == grp ? 2 * (li >> 3) + (li & 1) : -1;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (e == dpos) a[q][e >> 1][e & 1] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            a[q][e >> 1][e & 1], bx[t][e >> 1][e & 1], acc[q][t], 0, 0, 0);
+        };
+        if (nfull > 0) {
+            f64x2 v1[U][TPW][2];
+            f64x2 b1[U][NT][2];
+            auto consume = [&](f64x2 (&v)[U][TPW][2], f64x2 (&bx)[U][NT][2], int64_t t0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) mfma_block(v[u], bx[u], wave + W * (t0 + u));
+            };
+            if (!preloaded) issue(arow, v0, b0, 0);
+            int64_t t = 0;
+            for (; t + 3 * U <= nfull; t += 2 * U) {
+                issue(arow, v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v0, b0, t);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(arow, v0, b0, t + 2 * U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (t + 2 * U <= nfull) {
+                issue(arow, v1, b1, t + U);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v0, b0, t);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(v1, b1, t + U);
+            } else {
+                consume(v0, b0, t);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        gptr<double> arow_next[TPW];
+        const bool more = pr + 16 * TPW < r1;
+        if (more) rows_of(arow_next, pr + 16 * TPW);
+        preloaded = more && nfull > 0;
+        if (preloaded) issue(arow_next, v0, b0, 0);
+        // Remaining blocks of this wave (the ragged tail).
+        for (int64_t b = wave + W * nfull; b < nb; b += W) {
+            f64x2 a[TPW][2];
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                if (b < nbf) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        a[q][j] = __builtin_nontemporal_load(
+                            (gptr<f64x2>)(arow[q] + b * BW + 8 * j));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int off = 8 * (e >> 1) + (e & 1);
+                        const int64_t col = b * BW + 2 * grp + off;
+                        a[q][e >> 1][e & 1] = col < n ? arow[q][b * BW + off] : 0.0;
+                    }
+                }
+            }
+            f64x2 bx[NT][2];
+            load_b(bx, b);  // zero padded past n
+            mfma_block(a, bx, b);
+        }
+        // Add the W partial tiles in wave order.
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[(((wave * TPW + q) * NT + t) * 4 + v) * 64 + lane] = acc[q][t][v];
+        constexpr int EPT = TPW * NT * 256 / (W * 64);
+        static_assert(EPT * W * 64 == TPW * NT * 256, "epilogue elements per thread");
+        double e_xo[EPT], e_b[EPT], e_d[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * W * 64;
+            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+            const int q = qt / NT, t = qt - q * NT;
+            const int64_t i = pr + 16 * q + ri;
+            const int c = t * 16 + cc;
+            const bool ok = i < r1 && c < k;
+            const int64_t is = ok ? i : r0;
+            const int cs = ok ? c : 0;
+            e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
+            e_b[u] = *gbl((const double*)S.bT + (int64_t)cs * xld + is);
+            e_d[u] = *gbl((const double*)S.diag + is);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * W * 64;
+            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+            const int q = qt / NT, t = qt - q * NT;
+            const int l = 16 * (ri & 3) + cc, v = ri >> 2;
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
+            const int64_t i = pr + 16 * q + ri;
+            const int c = t * 16 + cc;
+            if (i < r1 && c < k) {
+                const double xo = e_xo[u];
+                const double xn = (e_b[u] - s) / e_d[u];
+                *gout(xout + (int64_t)c * xld + i) = xn;
+                const double dd = fabs(xn - xo);
+                const uint64_t db = dbits(dd), mb = dbits(fabs(xn));
+                dmax = db > dmax ? db : dmax;
+                xmax = mb > xmax ? mb : xmax;
+                sq += dd * dd;
+            }
+        }
+        __syncthreads();  // red is reused by the next pass
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) arow[q] = arow_next[q];
+        }
+    }
+}
+
+// The row sweep of a launch's element type.
+template <typename TA, int KT, int W, int TPW, int U>
+__device__ __forceinline__ void sweep_any(const BSys& S, int64_t r0, int64_t r1, const void* xin,
+                                          void* xout, void* red, int tid, int wave,
+                                          uint64_t& dmax, uint64_t& xmax, double& sq) {
+    if constexpr (std::is_same<TA, double>::value)
+        sweep_rows_f64<KT, W, TPW, U>(S, r0, r1, (const double*)xin, (double*)xout,
+                                      (double*)red, tid, wave, dmax, xmax, sq);
+    else
+        sweep_rows<TA, KT, W, TPW, U>(S, r0, r1, (const float*)xin, (float*)xout, (float*)red,
+                                      tid, wave, dmax, xmax, sq);
+}
+
+// ---------------------------------------------------------------------------
 // The persistent kernel.
 //   W   waves per workgroup (they split the columns of every tile)
 //   TPW 16-row tiles per pass (they share every B operand load)
@@ -424,8 +668,9 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
 //   MINB workgroups per CU the register budget is sized for
 template <typename TA, int KT, int W, int TPW, int U, int MINB>
 __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
+    using TX = typename IterOf<TA>::T;
     constexpr int NT = KT / 16;                // 16-column output tiles
-    __shared__ float red[W * TPW * NT * 256];
+    __shared__ TX red[W * TPW * NT * 256];
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ uint32_t s_flag;
@@ -468,19 +713,19 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
         const int64_t xld = S.xld;
         const int k = S.k;
         const bool split = S.nwg > 1;
-        const float* xfinal = S.buf0;
+        const TX* xfinal = (const TX*)S.buf0;
         int32_t final_k = 0;
         uint32_t final_stop = STOP_RUNNING;
         double final_delta = -1.0;
         bool failed = false;
 
         for (int sweep = 1; sweep <= S.max_iter; ++sweep) {
-            const float* xin = (sweep & 1) ? S.buf0 : S.buf1;
-            float* xout = (sweep & 1) ? S.buf1 : S.buf0;
+            const TX* xin = (const TX*)((sweep & 1) ? S.buf0 : S.buf1);
+            TX* xout = (TX*)((sweep & 1) ? S.buf1 : S.buf0);
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            sweep_rows<TA, KT, W, TPW, U>(S, job.r0, job.r1, xin, xout, red, tid, wave, dmax,
-                                          xmax, sq);
+            sweep_any<TA, KT, W, TPW, U>(S, job.r0, job.r1, xin, xout, red, tid, wave, dmax,
+                                         xmax, sq);
             // ---- workgroup reduction of the distance statistics
             dmax = wmax(dmax);
             xmax = wmax(xmax);
@@ -573,11 +818,11 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
         // Copy this workgroup's rows of the final iterate to the caller's X.
         // Every thread of the workgroup wrote its share of them before the
         // barriers that closed the last sweep.
-        const float* xsrc = final_k > 0 ? xfinal : S.buf0;
+        const TX* xsrc = final_k > 0 ? xfinal : (const TX*)S.buf0;
         for (int64_t e = tid; e < (job.r1 - job.r0) * k; e += W * 64) {
             const int64_t i = job.r0 + e / k;
             const int c = (int)(e % k);
-            S.X[i * S.ldx + c] = xsrc[(int64_t)c * xld + i];
+            ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * xld + i];
         }
         if (tid == 0 && job.rank == 0) {
             __hip_atomic_store(&st->status, final_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -602,8 +847,9 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 // items in round r + 1.  The loop ends one round after the last system stops.
 template <typename TA, int KT, int W, int TPW, int U, int MINB>
 __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
+    using TX = typename IterOf<TA>::T;
     constexpr int NT = KT / 16;
-    __shared__ float red[W * TPW * NT * 256];
+    __shared__ TX red[W * TPW * NT * 256];
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ int32_t s_item, s_done;
@@ -648,12 +894,12 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                 // stopped after sweep r - 1: this item's rows of the final iterate
                 if (bad) continue;
                 const BSys S = p.sys[item.sys];
-                const float* xsrc = ((r - 1) & 1) ? S.buf1 : S.buf0;
+                const TX* xsrc = (const TX*)(((r - 1) & 1) ? S.buf1 : S.buf0);
                 const int k = S.k;
                 for (int64_t e = tid; e < (int64_t)(item.r1 - item.r0) * k; e += W * 64) {
                     const int64_t i = item.r0 + e / k;
                     const int c = (int)(e % k);
-                    S.X[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
+                    ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
                 }
                 continue;
             }
@@ -662,10 +908,10 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
             if (!bad) {
-                const float* xin = (r & 1) ? S.buf0 : S.buf1;
-                float* xout = (r & 1) ? S.buf1 : S.buf0;
-                sweep_rows<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
-                                              dmax, xmax, sq);
+                const TX* xin = (const TX*)((r & 1) ? S.buf0 : S.buf1);
+                TX* xout = (TX*)((r & 1) ? S.buf1 : S.buf0);
+                sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
+                                             dmax, xmax, sq);
             }
             dmax = wmax(dmax);
             xmax = wmax(xmax);
@@ -788,6 +1034,7 @@ constexpr int kBU = 1;   // A blocks per pipeline stage (each block is two loads
 //   deep  one workgroup per CU (the register file doubles, accumulators move
 //         to AGPRs) and 4 tiles per pass everywhere, so each B operand load
 //         serves 4 tiles.  Few large systems: less L2 traffic per A byte.
+//   FP64 A takes 2 tiles per pass in the wide shape, 4 in the deep one.
 template <typename TA>
 constexpr int tiles_per_pass(int kt, int variant) {
     return (variant == 1 || (kt <= 16 && sizeof(TA) == 4)) ? 4 : 2;
@@ -796,10 +1043,13 @@ constexpr int tiles_per_pass(int kt, int variant) {
 // Shape parameters seen by the host planner: tiles per pass and the columns
 // one wave covers per pipeline round trip.
 int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 0) return tiles_per_pass<double>(kt, variant);
     return a_dtype == 1 ? tiles_per_pass<float>(kt, variant) : tiles_per_pass<bf16_t>(kt, variant);
 }
 int batched_unroll(int32_t) { return 2 * kBU; }
-int batched_block_cols(int32_t a_dtype) { return kBW * (a_dtype == 1 ? 32 : 64); }
+int batched_block_cols(int32_t a_dtype) {
+    return kBW * (a_dtype == 0 ? 16 : (a_dtype == 1 ? 32 : 64));
+}
 
 template <typename TA, int KT>
 static const void* batched_fn(int variant) {
@@ -808,6 +1058,8 @@ static const void* batched_fn(int variant) {
 }
 
 static const void* pick(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 0)
+        return kt <= 16 ? batched_fn<double, 16>(variant) : batched_fn<double, 32>(variant);
     if (a_dtype == 1)
         return kt <= 16 ? batched_fn<float, 16>(variant) : batched_fn<float, 32>(variant);
     if (a_dtype == 2)
@@ -829,7 +1081,10 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
                                 int32_t count, int64_t max_n, hipStream_t s) {
     int64_t bx = (max_n + 32 + 255) / 256;
     if (bx > 64) bx = 64;
-    if (a_dtype == 1)
+    if (a_dtype == 0)
+        hipLaunchKernelGGL((k_batched_setup<double>), dim3((unsigned)bx, count), dim3(256), 0, s,
+                           sys, st, kt);
+    else if (a_dtype == 1)
         hipLaunchKernelGGL((k_batched_setup<float>), dim3((unsigned)bx, count), dim3(256), 0, s,
                            sys, st, kt);
     else
@@ -845,6 +1100,8 @@ static const void* rounds_fn(int variant) {
 }
 
 static const void* pick_rounds(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 0)
+        return kt <= 16 ? rounds_fn<double, 16>(variant) : rounds_fn<double, 32>(variant);
     if (a_dtype == 1)
         return kt <= 16 ? rounds_fn<float, 16>(variant) : rounds_fn<float, 32>(variant);
     if (a_dtype == 2)

@@ -125,22 +125,23 @@ hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t 
 // ---------------------------------------------------------------------------
 // Batched persistent sweeps (MFMA tiles), one launch for many systems.
 
-// Per-system descriptor (device copy).  A is FP32 or BF16 (the launch's
-// dtype); B, X and the iterate buffers are FP32.  The iterate buffers hold X
-// transposed: kt rows (16 or 32) of xld >= n floats, padding zero.
+// Per-system descriptor (device copy).  A is FP64, FP32 or BF16 (the
+// launch's dtype); B, X, the iterate buffers and the diagonal are FP64 for an
+// FP64 launch and FP32 otherwise (the iterate type).  The iterate buffers
+// hold X transposed: kt rows (16 or 32) of xld >= n values, padding zero.
 struct BSys {
     const void* A;
     int64_t lda;
-    const float* B;
+    const void* B;
     int64_t ldb;
-    float* X;          // caller's output (ldx), written once at the end
+    void* X;           // caller's output (ldx), written once at the end
     int64_t ldx;
-    const float* X0;   // caller's initial approximation (ldx), or null for zero
-    float* buf0;       // x^(0) on entry (transposed); ping-pong with buf1
-    float* buf1;
-    float* bT;         // B transposed (kt x xld, padding zero)
-    int64_t xld;       // leading dimension of the transposed iterate (multiple of 32)
-    const float* diag;
+    const void* X0;    // caller's initial approximation (ldx), or null for zero
+    void* buf0;        // x^(0) on entry (transposed); ping-pong with buf1
+    void* buf1;
+    void* bT;          // B transposed (kt x xld, padding zero)
+    int64_t xld;       // leading dimension of the transposed iterate (multiple of 64)
+    const void* diag;
     int64_t n;
     int32_t k;
     int32_t nwg;       // workgroups sharing this system (1 = owned by one WG)

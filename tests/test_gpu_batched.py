@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import REL_F32, dev, host, rel_err, say
+from gpu_util import REL_F32, REL_F64, dev, host, rel_err, say, tie_margin
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,18 @@ def jac(gpu):
 def _sys32(n, k, seed, mode=synth.ADDITIVE, lo=1.0, hi=2.0):
     A32, Xt, B32 = synth.dominant_f32(n, k, seed, mode, lo, hi)
     return A32, Xt, B32
+
+
+def _sys_dev(n, k, seed, dtype):
+    """A dominant system on the device in the launch's types: FP64 A, B for
+    "f64"; FP32 B with FP32 or BF16 A otherwise."""
+    import torch
+    if dtype == "f64":
+        A, _, B = synth.dominant(n, k, seed, synth.ADDITIVE, 1.0, 2.0)
+        return dev(A), dev(B)
+    A32, _, B32 = _sys32(n, k, seed)
+    A = dev(A32)
+    return (A.to(torch.bfloat16) if dtype == "bf16" else A), dev(B32)
 
 
 def _oracle32(A32, B32, tol, cap=500):
@@ -74,23 +86,20 @@ def test_batch_invariance_bitwise(jac):
     assert torch.equal(X, xs[0]) and info["iterations"] == infos[0]["iterations"]
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
 def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
     """The wide (two workgroups per CU) and deep (one per CU, four tiles per
     pass) kernel shapes sum every element in the same order: bitwise the
     same X and counts."""
     import torch
     shapes = [(700, 32), (64, 5), (2048, 16), (300, 1), (1500, 9)]
-    sysl = []
-    for idx, (n, k) in enumerate(shapes):
-        A32, _, B32 = _sys32(n, k, 950 + idx)
-        A = dev(A32)
-        sysl.append((A.to(torch.bfloat16) if dtype == "bf16" else A, dev(B32)))
+    sysl = [_sys_dev(n, k, 950 + idx, dtype) for idx, (n, k) in enumerate(shapes)]
+    tol = 1e-11 if dtype == "f64" else 1e-6
     out = {}
     for shape in ("wide", "deep"):
         monkeypatch.setenv("JACOBI_BATCHED_SHAPE", shape)
         say("batched shape", shape, dtype)
-        out[shape] = jac.solve_batched(sysl, tol=1e-6, max_iter=200)
+        out[shape] = jac.solve_batched(sysl, tol=tol, max_iter=200)
     monkeypatch.delenv("JACOBI_BATCHED_SHAPE")
     for i in range(len(shapes)):
         assert torch.equal(out["wide"][0][i], out["deep"][0][i]), shapes[i]
@@ -98,7 +107,7 @@ def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
         assert out["wide"][1][i]["status"] == jac.OK
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
 def test_schedules_bitwise(jac, dtype, monkeypatch):
     """The lockstep schedule (one sweep of every system per round, rows dealt
     out as work items) and the planned one (split systems with their own
@@ -110,18 +119,19 @@ def test_schedules_bitwise(jac, dtype, monkeypatch):
     import torch
     shapes = [(4000, 32), (700, 32), (64, 5), (2048, 16), (300, 1), (1500, 9), (1, 1), (33, 3)]
     sysl = []
+    vdt = np.float64 if dtype == "f64" else np.float32
+    tol = 1e-11 if dtype == "f64" else 1e-6
     for idx, (n, k) in enumerate(shapes):
-        A32, _, B32 = _sys32(n, k, 960 + idx)
-        A = dev(A32)
-        x0 = dev(np.random.default_rng(idx).uniform(-1, 1, size=(n, k)).astype(np.float32))
-        sysl.append((A.to(torch.bfloat16) if dtype == "bf16" else A, dev(B32), x0))
+        A, B = _sys_dev(n, k, 960 + idx, dtype)
+        x0 = dev(np.random.default_rng(idx).uniform(-1, 1, size=(n, k)).astype(vdt))
+        sysl.append((A, B, x0))
     bad = list(sysl)
     Bb = sysl[3][1].clone()
     Bb[17, 2] = float("nan")
     bad[3] = (sysl[3][0], Bb, sysl[3][2])
-    runs = [(sysl, dict(tol=1e-6, max_iter=200)), (sysl, dict(tol=1e-6, max_iter=0)),
-            (sysl, dict(tol=0.0, max_iter=3)), (bad, dict(tol=1e-6, max_iter=200)),
-            (sysl, dict(tol=1e-6, max_iter=200, norm="l2"))]
+    runs = [(sysl, dict(tol=tol, max_iter=200)), (sysl, dict(tol=tol, max_iter=0)),
+            (sysl, dict(tol=0.0, max_iter=3)), (bad, dict(tol=tol, max_iter=200)),
+            (sysl, dict(tol=tol, max_iter=200, norm="l2"))]
     for r, (batch, kw) in enumerate(runs):
         out = {}
         for sched in ("planned", "lockstep"):
@@ -315,3 +325,92 @@ def test_prepared_batch(jac):
             assert a["iterations"] == b["iterations"] and a["status"] == b["status"] == jac.OK
         for _, B in sysl:
             B.mul_(0.5)  # the next solve reads the new right-hand sides
+
+
+def test_f64_batch_parity(jac):
+    """FP64 systems in one persistent launch on FP64 MFMA tiles: uneven sizes
+    (n < 16, ragged tails, several passes and column blocks), k in 1..32, an
+    odd leading dimension; the FP64 counts equal the oracle's (when the tie
+    margin holds) and X agrees to 1e-12; the Euclidean norm in fixed-sweep
+    mode agrees too."""
+    import torch
+    shapes = [(1, 1), (5, 3), (16, 16), (17, 32), (100, 1), (255, 7), (256, 32), (513, 16),
+              (1000, 4), (1201, 32), (333, 9)]
+    tol = 1e-11
+    sysl, refs = [], []
+    for idx, (n, k) in enumerate(shapes):
+        A, _, B = synth.dominant(n, k, 1500 + idx, synth.ADDITIVE, 1.0, 2.0)
+        xo, io = oracle.jacobi(A, B, tol=tol, max_iter=500)
+        xl2, _ = oracle.jacobi(A, B, tol=0.0, max_iter=5, norm="l2")
+        pad = 1 if idx == len(shapes) - 1 else 0
+        big = torch.zeros((n, n + pad), dtype=torch.float64)
+        big[:, :n] = torch.from_numpy(A)
+        sysl.append((big.cuda()[:, :n], dev(B)))
+        refs.append((A, B, xo, io, xl2))
+    say("f64 batch")
+    xs, infos = jac.solve_batched(sysl, tol=tol, max_iter=500)
+    for (n, k), X, info, (A, B, xo, io, _) in zip(shapes, xs, infos, refs):
+        assert info["status"] == jac.OK == io["status"], (n, k, info)
+        if tie_margin(A, B, tol, io["iterations"]) > 1e-6:
+            assert info["iterations"] == io["iterations"], (n, k, info, io)
+        assert rel_err(host(X), xo) <= REL_F64, (n, k)
+    say("f64 batch l2")
+    xs, infos = jac.solve_batched(sysl, tol=0.0, max_iter=5, norm="l2")
+    for (n, k), X, info, ref in zip(shapes, xs, infos, refs):
+        assert info["iterations"] == 5 and info["status"] == jac.NOT_CONVERGED
+        assert rel_err(host(X), ref[4]) <= REL_F64, (n, k)
+
+
+def test_paper_workload_replay(jac):
+    """The shapes of the paper's serial timing table (n = 8 ... 512, FP64,
+    one right-hand side) at its fixed L = 10000 sweeps (tol = 0) in one
+    launch: every system runs exactly L sweeps and X agrees with the oracle's
+    L sweeps to 1e-12.  The inputs are dominant systems (the paper's own
+    U[0,1] inputs overflow long before L; see the next test)."""
+    ns = [8, 16, 32, 64, 128, 256, 512]
+    L = 10000
+    sysl, refs = [], []
+    for n in ns:
+        A, _, B = synth.dominant(n, 1, 1600 + n, synth.ADDITIVE, 1.0, 2.0)
+        sysl.append((dev(A), dev(B)))
+        refs.append((A, B))
+    say("paper workload replay")
+    xs, infos = jac.solve_batched(sysl, tol=0.0, max_iter=L)
+
+    def ref(r):
+        return oracle.jacobi(r[0], r[1], tol=0.0, max_iter=L)
+
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=7) as ex:
+        outs = list(ex.map(ref, refs))
+    for n, X, info, (xo, io) in zip(ns, xs, infos, outs):
+        assert info["status"] == jac.NOT_CONVERGED == io["status"], (n, info)
+        assert info["iterations"] == L == io["iterations"]
+        assert rel_err(host(X), xo) <= REL_F64, n
+
+
+def test_paper_inputs_diverge_per_system(jac):
+    """The paper's own inputs (A, B, X0 iid U[0,1], sec. 4) in one FP64
+    batch: every system overflows and stops with DIVERGED at the oracle's
+    sweep, on its own; a dominant system in the same batch converges as it
+    does alone."""
+    import torch
+    ns = [8, 16, 32, 64, 128, 256, 512]
+    sysl, refs = [], []
+    for n in ns:
+        A, b, x0 = synth.paper_uniform(n, 1700 + n)
+        sysl.append((dev(A), dev(b.reshape(n, 1)), dev(x0.reshape(n, 1))))
+        refs.append(oracle.jacobi(A, b, X0=x0, tol=1e-8, max_iter=10000)[1])
+    A, _, B = synth.dominant(300, 2, 1799, synth.ADDITIVE, 1.0, 2.0)
+    good = (dev(A), dev(B))
+    say("paper inputs diverge")
+    xs, infos = jac.solve_batched(sysl + [good], tol=1e-8, max_iter=10000)
+    for n, info, io in zip(ns, infos, refs):
+        assert io["status"] == jac.DIVERGED, (n, io)
+        assert info["status"] == jac.DIVERGED, (n, info)
+        # the overflow sweep can move by one with the summation order
+        assert abs(info["iterations"] - io["iterations"]) <= 1, (n, info, io)
+        assert not np.isfinite(info["final_delta"])
+    alone, ia = jac.solve_batched([good], tol=1e-8, max_iter=10000)
+    assert infos[-1]["status"] == jac.OK
+    assert torch.equal(alone[0], xs[-1]) and ia[0]["iterations"] == infos[-1]["iterations"]
