@@ -123,6 +123,8 @@ def main() -> int:
 
     if args.config != "c2":
         res = {"c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.config](args)
+        if args.calibrate_copy:
+            _calibrate_copy()
         print(json.dumps(res), flush=True)
         return 0
 
@@ -168,12 +170,7 @@ def main() -> int:
     elapsed = max(wall, gpu_ms / 1e3)
 
     if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        _calibrate_copy()
 
     per_sweep = sweep_bytes_f32(n)
     total_bytes = per_sweep * args.sweeps * args.steps
@@ -234,6 +231,18 @@ def main() -> int:
     print(json.dumps(res), flush=True)
     ctx.close()
     return 0
+
+
+def _calibrate_copy():
+    """One plain 1 GiB device-to-device copy: the reference kernel whose
+    hardware byte counters scale those of the measured kernels."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def _common(args, metric, value, unit, ms_per_step, dtype, config, higher=True):

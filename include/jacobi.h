@@ -272,7 +272,7 @@ JACOBI_API jacobi_status jacobi_serve_destroy(jacobi_server* srv);
  * memory (code that must not call hipMalloc: tight serving loops, harnesses
  * that forbid the allocator).  Same arguments, conventions and results as
  * jacobi_solve in PLAIN mode on the current HIP device, restricted to the
- * vector sweep path: k <= 4 right-hand sides, opt->mode = PLAIN,
+ * vector sweep path: k <= 2 right-hand sides, opt->mode = PLAIN,
  * opt->profile = 0 (other values: JACOBI_ERR_INVALID_ARG).  X, the count and
  * the distance are bitwise those of jacobi_solve for the same input.
  *
@@ -283,7 +283,7 @@ JACOBI_API jacobi_status jacobi_serve_destroy(jacobi_server* srv);
  * kp = k rounded up to a power of two), each rounded up to 256 bytes, with
  * 8-byte elements for F64 and 4-byte for F32/BF16; a larger n * k returns
  * JACOBI_ERR_INVALID_ARG with the sizes in jacobi_last_error() before any
- * device work (F64, k = 1: n up to about 980000).  Every call on a device
+ * device work (F64, k = 1: n up to about 980000; k = 2: about 590000).  Every call on a device
  * uses that device's one array, and the library serialises such calls with
  * a per-device lock; work of a call is complete when it returns (it waits on
  * `stream`), so it cannot be captured into a graph.  Calls that overlap on

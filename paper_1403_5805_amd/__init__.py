@@ -212,7 +212,7 @@ def solve_noalloc(A, B, x0=None, *, out=None, stream=None, raise_on_error: bool 
                   **opts):
     """jacobi_solve_noalloc: the plain solve with its workspace in the
     library's fixed per-device array (no device allocation by the library;
-    k <= 4, plain mode).  The caller provides `out` to avoid torch allocating
+    k <= 2, plain mode).  The caller provides `out` to avoid torch allocating
     the result.  Same arguments and results as solve()."""
     return solve(A, B, x0, out=out, stream=stream, raise_on_error=raise_on_error,
                  _noalloc=True, **opts)

@@ -148,6 +148,8 @@ jacobi_ctx* default_ctx(jacobi_status* st) {
     return g_default_ctx[dev];
 }
 
+int mfma_min_cols(int32_t) { return 3; }
+
 int kpad_for(int64_t k) {
     if (k <= 32) {
         int kt = 1;
@@ -301,8 +303,12 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
                                  hipStream_t s, jacobi_info* info) {
     // Several right-hand sides: the sweep is a real dense contraction, run
     // on MFMA tiles (FP32 for FP32/BF16 A, FP64 for FP64 A) by the
-    // persistent kernel.
-    if (k >= 8 && k <= 32 && o.profile == 0) {
+    // persistent kernel.  The vector kernel keeps one or two columns, where
+    // it streams faster (n = 16384, TB/s, vector / MFMA: FP64 k = 1 6.8 / 4.9,
+    // k = 2 5.9 / 4.9; FP32 k = 2 5.9 / 4.4; BF16 k = 2 3.6 / 3.4); from three
+    // columns its per-column reductions fall behind (k = 3: FP64 2.5, FP32
+    // 3.0, BF16 1.4 against 4.9, 4.3 and 3.4 on the tiles).
+    if (k >= mfma_min_cols(a_dtype) && k <= 32 && o.profile == 0) {
         BatchItem it{n, k, A, lda, B, ldb, X0, X, ldx, o.max_iter};
         jacobi_status st = run_batched(c, 1, &it, a_dtype, o, TEST_ABS, 0.0, s, info);
         if (st != JACOBI_OK) return st;

@@ -113,7 +113,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         grid = plan.grid;
     }
     if (grid > capacity) {
-        // a cooperative launch needs every workgroup resident at once
+        // the grid barriers need every workgroup resident at once
         set_error("batched plan of %d workgroups exceeds the resident grid %d", grid, capacity);
         return JACOBI_ERR_INTERNAL;
     }

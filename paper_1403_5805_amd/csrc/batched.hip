@@ -1,6 +1,6 @@
 // Persistent batched Jacobi sweeps on MFMA tiles (gfx950).
 //
-// One cooperative launch runs every sweep of many independent systems
+// One persistent launch runs every sweep of many independent systems
 // A_s X_s = B_s (each with k_s <= 32 right-hand sides).  The work of a sweep,
 // S = (A - D) X followed by x_new = (b - s) / a_ii (the component equation of
 // sec. 2 of the paper applied to every column), is a dense n x n by n x k
@@ -32,9 +32,13 @@
 //   * planned (k_batched): a large system is split over several workgroups
 //     that meet at a per-system barrier (atomic counter) after every sweep;
 //     small systems are owned whole by one workgroup and taken from a queue.
-// Launches are cooperative, so every workgroup is resident and the barrier
-// waits always end; a wall-clock bound turns a stuck wait into an error
-// instead of a hang.
+// Residency: the grid never exceeds the occupancy-derived count of
+// workgroups the device holds at once (workgroups per CU x CUs), so every
+// workgroup is dispatched while the others wait at a barrier (other kernels
+// running beside it only delay a dispatch: none of them waits for this one).
+// An ordinary launch gives that guarantee, so no cooperative launch is used.
+// A wall-clock bound on every barrier wait turns a wait that cannot end into
+// an error instead of a hang.
 #include <math.h>
 #include <stdint.h>
 
@@ -1125,7 +1129,7 @@ hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchAr
     if (!fn) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBW * 64), args, 0u, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBW * 64), args, 0, s);
 }
 
 hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
@@ -1134,7 +1138,7 @@ hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchA
     if (!fn) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBW * 64), args, 0u, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBW * 64), args, 0, s);
 }
 
 }  // namespace jac

@@ -101,6 +101,9 @@ struct PlainWs {
 
 // Padded column count of the iterate buffers for k right-hand sides.
 int kpad_for(int64_t k);
+// Fewest right-hand sides a plain solve of this A type runs on MFMA tiles
+// (fewer stay on the vector sweep kernel).
+int mfma_min_cols(int32_t a_dtype);
 
 // Plain Jacobi solve on the vector sweep kernel with the given workspace
 // (no allocation).  Arguments as jacobi_solve; the caller has validated them.

@@ -1,7 +1,7 @@
 // No-allocation variant of the plain solve, for callers that cannot allocate
 // device memory (tight serving loops, harnesses that forbid the allocator).
 //
-// It runs the vector sweep path of jacobi_solve (one to four right-hand
+// It runs the vector sweep path of jacobi_solve (one or two right-hand
 // sides) with its whole workspace -- control block, reduction slots, partial
 // sums, diagonal and the two iterate buffers -- carved out of one file-scope
 // device array.  Each device holds its own copy of the array (allocated with
@@ -22,7 +22,7 @@ namespace {
 
 constexpr size_t kScratchBytes = JACOBI_NOALLOC_MAX_BYTES;
 constexpr int kMaxDevices = 64;
-constexpr int64_t kMaxCols = 4;
+constexpr int64_t kMaxCols = 2;
 
 }  // namespace
 

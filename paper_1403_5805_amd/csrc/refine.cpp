@@ -68,12 +68,12 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     HIP_TRY(c->scal.ensure(64));
     HIP_TRY(c->alo.ensure(elo * (size_t)n * ld_lo));
     // Several right-hand sides: the residual runs on FP64 MFMA tiles and (from
-    // 8 columns) the inner solve on the FP32 MFMA kernel; one column streams
-    // through the vector kernels.
+    // 3 columns, as in the plain solve) the inner solve on the FP32 MFMA
+    // kernel; one column streams through the vector kernels.
     // (k = 1 measured 20% slower on the MFMA residual: the FP64 tiles pad one
     // column to sixteen, and the vector kernel streams a single column well.)
     const bool mfma_resid = k >= 2 && k <= 32;
-    const bool mfma_inner = k >= 8 && k <= 32;
+    const bool mfma_inner = k >= mfma_min_cols(lo) && k <= 32;
     if (mfma_resid) HIP_TRY(c->xT.ensure(resid_xT_bytes(n, k)));
 
     HIP_TRY(hipEventRecord(c->ev_begin, s));

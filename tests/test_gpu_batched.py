@@ -81,7 +81,7 @@ def test_batch_invariance_bitwise(jac):
         x1, i1 = jac.solve_batched([s], tol=1e-6, max_iter=200)
         assert torch.equal(x1[0], xs[i]), shapes[i]
         assert i1[0]["iterations"] == infos[i]["iterations"]
-    # the single-system entry point routes k >= 8 FP32 to the same kernel
+    # the single-system entry point routes k >= 3 FP32 to the same kernel
     X, info = jac.solve(sysl[0][0], sysl[0][1], tol=1e-6, max_iter=200)
     assert torch.equal(X, xs[0]) and info["iterations"] == infos[0]["iterations"]
 

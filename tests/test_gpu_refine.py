@@ -56,7 +56,7 @@ def _padded(A, pad):
                                      (1000, 8, 0), (777, 17, 1), (2047, 32, 0)])
 def test_refine_multi_rhs_parity(jac, n, k, pad):
     """Several right-hand sides: the FP64 residual runs on MFMA tiles (k >= 2)
-    and the inner solve on the FP32 MFMA kernel (k >= 8); odd leading
+    and the inner solve on the FP32 MFMA kernel (k >= 3); odd leading
     dimensions take the unaligned load path; n = 1 and ragged n cover the
     partial tiles and column blocks."""
     mode = synth.ADDITIVE if n < 32 else synth.MULTIPLICATIVE
@@ -268,7 +268,7 @@ def test_reduced_copy_rounding_bitwise(jac, fmt, n, k, pad, x0):
     the conversion kernel (x0 = None, or k > 1) and the first residual pass
     that writes A_lo while it streams A (an explicit zero x0 with one column),
     aligned and odd leading dimensions, the vector sweep (k < 8) and the MFMA
-    sweep (k >= 8)."""
+    sweep (k >= 3)."""
     A, b = _rounding_system(n, fmt, 4500 + n + k + pad)
     B = np.repeat(b[:, None], k, axis=1) * (1.0 + (np.arange(k) % 2))[None, :]
     lo = oracle.round_bf16(A) if fmt == "bf16" else A.astype(np.float32).astype(np.float64)

@@ -61,8 +61,8 @@ def _same(jac, case, **opts):
 
 @pytest.mark.parametrize("first,second", [
     ((1536, 2, "f64", 11, 0, False), (300, 1, "f64", 12, 0, False)),
-    ((2001, 4, "f32", 13, 1, True), (97, 3, "f32", 14, 1, False)),
-    ((1200, 1, "bf16", 15, 0, False), (64, 1, "bf16", 16, 1, True)),
+    ((2001, 2, "f32", 13, 1, True), (97, 1, "f32", 14, 1, False)),
+    ((1200, 1, "bf16", 15, 0, False), (64, 2, "bf16", 16, 1, True)),
 ])
 def test_noalloc_matches_solve_twice(jac, first, second):
     """Two calls in a row (the second smaller) equal jacobi_solve bitwise; the
@@ -99,7 +99,7 @@ def test_noalloc_validation_and_edges(jac):
 
 
 def test_noalloc_refuses_before_device_work(jac):
-    """Shapes whose workspace exceeds the fixed array, k > 4, refinement and
+    """Shapes whose workspace exceeds the fixed array, k > 2, refinement and
     per-sweep profiling are refused with ERR_INVALID_ARG before any device
     work (the device pointers of a small case stand in for the large one:
     nothing is read)."""
@@ -110,9 +110,9 @@ def test_noalloc_refuses_before_device_work(jac):
     info = _lib.Info()
     p = ctypes.c_void_p
     say("noalloc refusals")
-    n = 400000  # F64, k = 4: about 29 MB of workspace
-    st = lib.jacobi_solve_noalloc(n, 4, jac.F64, p(Ad.data_ptr()), n, p(Bd.data_ptr()), 4, None,
-                                  p(Bd.data_ptr()), 4, ctypes.byref(o), None, ctypes.byref(info))
+    n = 700000  # F64, k = 2: about 30 MB of workspace
+    st = lib.jacobi_solve_noalloc(n, 2, jac.F64, p(Ad.data_ptr()), n, p(Bd.data_ptr()), 2, None,
+                                  p(Bd.data_ptr()), 2, ctypes.byref(o), None, ctypes.byref(info))
     assert st == jac.ERR_INVALID_ARG and "workspace" in jac.last_error()
     for kw in ({"mode": "refine"}, {"profile": True}):
         o = jac.make_options(**kw)
@@ -121,6 +121,6 @@ def test_noalloc_refuses_before_device_work(jac):
                                       ctypes.byref(info))
         assert st == jac.ERR_INVALID_ARG, kw
     o = jac.make_options()
-    st = lib.jacobi_solve_noalloc(64, 5, jac.F64, p(Ad.data_ptr()), 64, p(Bd.data_ptr()), 5, None,
-                                  p(Bd.data_ptr()), 5, ctypes.byref(o), None, ctypes.byref(info))
+    st = lib.jacobi_solve_noalloc(64, 3, jac.F64, p(Ad.data_ptr()), 64, p(Bd.data_ptr()), 3, None,
+                                  p(Bd.data_ptr()), 3, ctypes.byref(o), None, ctypes.byref(info))
     assert st == jac.ERR_INVALID_ARG
