@@ -103,7 +103,10 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     const size_t ea = a_dtype == JACOBI_F64 ? 8 : (a_dtype == JACOBI_F32 ? 4 : 2);
     const size_t ex = a_dtype == JACOBI_F64 ? 8 : 4;  // iterate element
     if (sched == 1) {
-        ip = make_items(ns, capacity, tpp, (int)ea);
+        int groups = 1;  // JACOBI_BATCHED_GROUPS=8 groups the items by XCD
+        if (const char* env = getenv("JACOBI_BATCHED_GROUPS"))
+            groups = std::min(kMaxGroups, std::max(1, atoi(env)));
+        ip = make_items(ns, capacity, tpp, (int)ea, groups);
         grid = ip.grid;
     } else {
         int max_split = 1 << 30;
@@ -129,13 +132,14 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     }
     // device metadata: [sys | st | schedule tables (uploaded) | partial sums]
     //   sched 0 tables: jobs | job_off | queue head (16 bytes) + queue
-    //   sched 1 tables: items | BCtl
+    //   sched 1 tables: items | group offsets | BCtl
     const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
     size_t job_b = 0, off_b = 0, q_b = 0, parts_b = 0;
     if (sched == 1) {
         job_b = align(sizeof(BJob) * std::max<size_t>(1, ip.items.size()));
+        off_b = align(sizeof(int32_t) * ip.g_off.size());
         q_b = align(sizeof(BCtl));
-        parts_b = align(sizeof(double) * std::max<size_t>(1, ip.items.size()));
+        parts_b = align(sizeof(double) * 2 * std::max<size_t>(1, ip.items.size()));
     } else {
         job_b = align(sizeof(BJob) * std::max<size_t>(1, plan.jobs.size()));
         off_b = align(sizeof(int32_t) * plan.job_off.size());
@@ -209,10 +213,11 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     char* ht = h + sys_b + st_b;
     if (sched == 1) {
         std::memcpy(ht, ip.items.data(), sizeof(BJob) * ip.items.size());
+        std::memcpy(ht + job_b, ip.g_off.data(), sizeof(int32_t) * ip.g_off.size());
         BCtl ctl;
         std::memset(&ctl, 0, sizeof(ctl));
         ctl.active = (uint32_t)active0;
-        std::memcpy(ht + job_b, &ctl, sizeof(ctl));
+        std::memcpy(ht + job_b + off_b, &ctl, sizeof(ctl));
     } else {
         if (!plan.jobs.empty()) std::memcpy(ht, plan.jobs.data(), sizeof(BJob) * plan.jobs.size());
         std::memcpy(ht + job_b, plan.job_off.data(), sizeof(int32_t) * plan.job_off.size());
@@ -238,6 +243,8 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         ba.items = d_jobs;
         ba.item_parts = d_parts;
         ba.ctl = (BCtl*)d_q;
+        ba.group_off = d_off;
+        ba.ngroups = ip.ngroups;
         ba.nitems = (int32_t)ip.items.size();
         ba.active0 = active0;
         ba.max_rounds = max_rounds;

@@ -17,6 +17,11 @@
 //     waves; on rows that are not 16-byte aligned the contiguous 64-byte runs
 //     measured 10% faster than 32-byte runs per lane); one block feeds 8
 //     (FP32) or 16 (BF16) MFMA k-steps;
+//   * A is read with ordinary (temporal) loads: on a row that is not 16-byte
+//     aligned a block spans two cache lines, each shared with the neighbouring
+//     wave's block, and non-temporal loads fetched such lines twice (64
+//     systems of 4095 rows: 1.74x the bytes of A from the fabric, 3.2 TB/s;
+//     with ordinary loads 1.13x and 4.2 TB/s; aligned rows also gain);
 //   * the iterate is kept transposed in global memory (column c of X is a
 //     contiguous row of xld floats, zero padded), so the matching B operand
 //     of 4 k-steps is one 16-byte load that hits the L2 (X is small and every
@@ -260,8 +265,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
             for (int q = 0; q < TPW; ++q)
 #pragma unroll
                 for (int j = 0; j < LPL; ++j)
-                    v[u][q][j] = __builtin_nontemporal_load(
-                        (gptr<u32x4>)(rows[q] + b * BW + j * 4 * V16));
+                    v[u][q][j] = *(gptr<u32x4>)(rows[q] + b * BW + j * 4 * V16);
             load_b(bx[u], b);
         }
     };
@@ -367,8 +371,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
                 if (b < nbf) {
 #pragma unroll
                     for (int j = 0; j < LPL; ++j) {
-                        const u32x4 v = __builtin_nontemporal_load(
-                            (gptr<u32x4>)(arow[q] + b * BW + j * 4 * V16));
+                        const u32x4 v = *(gptr<u32x4>)(arow[q] + b * BW + j * 4 * V16);
                         unpack<TA>(v, a[q] + j * V16);
                     }
                 } else {
@@ -496,8 +499,7 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
             for (int q = 0; q < TPW; ++q)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    v[u][q][j] = __builtin_nontemporal_load(
-                        (gptr<f64x2>)(rows[q] + b * BW + 8 * j));
+                    v[u][q][j] = *(gptr<f64x2>)(rows[q] + b * BW + 8 * j);
             load_b(bx[u], b);
         }
     };
@@ -580,8 +582,7 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
                 if (b < nbf) {
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        a[q][j] = __builtin_nontemporal_load(
-                            (gptr<f64x2>)(arow[q] + b * BW + 8 * j));
+                        a[q][j] = *(gptr<f64x2>)(arow[q] + b * BW + 8 * j);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
@@ -840,15 +841,25 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 
 // ---------------------------------------------------------------------------
 // The lockstep schedule.  Round r is sweep r of every system still running:
-// the rows of all systems are cut into work items (largest systems first) and
-// every workgroup takes the next item from one atomic ticket counter until
-// the round's items are gone, then waits at one grid barrier.  No workgroup
-// ever waits for one system: a few large systems and many small ones load the
-// chip evenly.  Each item adds its distance maxima to its system's slot (and
-// its sum of squares to its own slot for the Euclidean norm); the item that
-// completes a system's round, found by a per-system ticket, applies the stop
-// test.  A system that stops after sweep r is copied to the caller's X by its
-// items in round r + 1.  The loop ends one round after the last system stops.
+// the rows of all systems are cut into work items and every workgroup takes
+// items from atomic ticket counters until the round's items are gone, then
+// waits at one grid barrier.  No workgroup ever waits for one system: a few
+// large systems and many small ones load the chip evenly.  The items form one
+// group per XCD (each system's items in one group, largest systems first);
+// workgroup g, which runs on XCD g % ngroups, drains its own group's queue
+// and then helps the other groups in turn, so a system's iterate, read in
+// full by each of its items, is mostly read from one XCD's L2.
+//
+// Each item adds its distance maxima to its system's slot for the round (and
+// its sum of squares to its own slot for the Euclidean norm).  The stop test
+// of sweep r - 1 is taken at the start of round r, after the grid barrier
+// has made every item's contribution visible, by every item of the system
+// alike (the Euclidean sum in item order, so the distance does not depend on
+// the schedule): no item waits for, or fences against, the other items of
+// its system inside a round.  A system that stops after sweep r - 1 has its
+// rows copied to the caller's X by its items in round r; its first item
+// records the outcome.  The loop ends after the round in which the last
+// system is copied out.
 template <typename TA, int KT, int W, int TPW, int U, int MINB>
 __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     using TX = typename IterOf<TA>::T;
@@ -856,48 +867,118 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     __shared__ TX red[W * TPW * NT * 256];
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
-    __shared__ int32_t s_item, s_done;
-    __shared__ bool s_bad;
+    __shared__ int32_t s_item, s_act;
+    __shared__ uint32_t s_flag;
+    __shared__ double s_delta;
     __shared__ uint32_t s_active, s_abort;
+    enum { ACT_SKIP = 0, ACT_COPY = 1, ACT_STOP = 2, ACT_SWEEP = 3, ACT_INVALID = 4 };
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint64_t per_round = (uint64_t)p.nitems + gridDim.x;  // tickets taken per round
-    bool last = p.active0 == 0;  // a round that only copies results out
     for (int r = 1;; ++r) {
-        const uint64_t base = (uint64_t)(r - 1) * per_round;
+        const int par = r & 1;
+        // the other parity's tickets were last drawn in round r - 1, which
+        // every workgroup has left; they are next drawn in round r + 1
+        if (blockIdx.x == 0 && tid < p.ngroups)
+            __hip_atomic_store(&p.ctl->qhead[par ^ 1][tid], 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        int qoff = 0;  // thread 0: groups of this round found empty, own group first
         for (;;) {
-            __syncthreads();  // s_item and red are reused
+            __syncthreads();  // the shared words and red are reused
             if (tid == 0) {
-                // One thread reads the item's state for the whole workgroup:
-                // `done` of this item's system changes only after its last
-                // item of the round, so it is fixed while this item runs.
-                const uint64_t h = __hip_atomic_fetch_add(&p.ctl->head, (uint64_t)1,
-                                                          __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t it = h - base < (uint64_t)p.nitems ? (int32_t)(h - base) : -1;
+                int32_t it = -1;
+                while (qoff < p.ngroups) {
+                    const int g = (int)((blockIdx.x + qoff) % (uint32_t)p.ngroups);
+                    const int32_t cnt = p.group_off[g + 1] - p.group_off[g];
+                    const uint32_t t = cnt > 0 ? __hip_atomic_fetch_add(
+                                                     &p.ctl->qhead[par][g], 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                               : 0u;
+                    if ((int32_t)t < cnt) {
+                        it = p.group_off[g] + (int32_t)t;
+                        break;
+                    }
+                    ++qoff;
+                }
                 s_item = it;
                 if (it >= 0) {
-                    BState* st = &p.st[p.items[it].sys];
-                    s_done = __hip_atomic_load(&st->done, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    s_bad = __hip_atomic_load(&st->bad_diag, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX ||
-                            __hip_atomic_load(&st->bad_rhs, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX;
+                    // What this item does in round r, decided by one thread
+                    // for the workgroup.  `done` is 0 while the system runs,
+                    // r when it is copied out in this round (max_iter = 0,
+                    // or set by its first item below: either way the same
+                    // action), and otherwise final.
+                    const int32_t sys = p.items[it].sys;
+                    BState* st = &p.st[sys];
+                    const int32_t done =
+                        __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const bool bad = __hip_atomic_load(&st->bad_diag, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX ||
+                                     __hip_atomic_load(&st->bad_rhs, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX;
+                    int32_t act = ACT_SKIP;
+                    uint32_t flag = STOP_RUNNING;
+                    double delta = -1.0;
+                    if (done == r) {
+                        act = bad ? ACT_SKIP : ACT_COPY;
+                    } else if (done == 0) {
+                        if (bad) {
+                            act = ACT_INVALID;
+                        } else if (r == 1) {
+                            act = ACT_SWEEP;
+                        } else {
+                            // the stop test of sweep r - 1
+                            const int32_t it0 = p.sys[sys].it0, it1 = p.sys[sys].it1;
+                            const int32_t norm = p.sys[sys].norm;
+                            const int slot = (r - 1) % 3;
+                            const uint64_t D = __hip_atomic_load(&st->dmax[slot], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                            const uint64_t M = __hip_atomic_load(&st->xmax[slot], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                            if (norm == 1) {
+                                const double* ip = p.item_parts + (size_t)((r - 1) & 1) * p.nitems;
+                                double Q = 0.0;  // item order: independent of the schedule
+                                for (int32_t j = it0; j < it1; ++j)
+                                    Q += __hip_atomic_load(&ip[j], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                                delta = sqrt(Q);
+                            } else {
+                                delta = bitsd(D);
+                            }
+                            const int32_t test = p.sys[sys].test;
+                            if (!isfinite(delta))
+                                flag = STOP_DIVERGED;
+                            else if (test == TEST_ABS ? (delta < p.sys[sys].tol)
+                                                      : (delta <= p.sys[sys].rel * bitsd(M)))
+                                flag = STOP_CONVERGED;
+                            act = (flag != STOP_RUNNING || r - 1 == p.sys[sys].max_iter)
+                                      ? ACT_STOP
+                                      : ACT_SWEEP;
+                        }
+                    }
+                    s_act = act;
+                    s_flag = flag;
+                    s_delta = delta;
                 }
             }
             __syncthreads();
             const int32_t it = s_item;
             if (it < 0) break;
+            const int32_t act = s_act;
+            if (act == ACT_SKIP) continue;
             const BJob item = p.items[it];
             BState* st = &p.st[item.sys];
-            const int32_t done = s_done;
-            const bool bad = s_bad;
-            if (done == r) {
+            const BSys S = p.sys[item.sys];
+            const bool first = it == S.it0;
+            if (act == ACT_INVALID) {
+                if (first && tid == 0) {
+                    __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+                continue;
+            }
+            if (act == ACT_COPY || act == ACT_STOP) {
                 // stopped after sweep r - 1: this item's rows of the final iterate
-                if (bad) continue;
-                const BSys S = p.sys[item.sys];
                 const TX* xsrc = (const TX*)(((r - 1) & 1) ? S.buf1 : S.buf0);
                 const int k = S.k;
                 for (int64_t e = tid; e < (int64_t)(item.r1 - item.r0) * k; e += W * 64) {
@@ -905,18 +986,34 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                     const int c = (int)(e % k);
                     ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
                 }
+                if (act == ACT_STOP && first && tid == 0) {
+                    __hip_atomic_store(&st->status, s_flag, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st->iterations, r - 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st->final_delta, dbits(s_delta), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st->done, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
                 continue;
             }
-            if (done != 0 || last) continue;
-            const BSys S = p.sys[item.sys];
+            // ACT_SWEEP: sweep r of this item's rows
+            if (first && tid == 0) {
+                // slot (r + 1) % 3 was last read in round r - 1; round r + 1 fills it
+                const int nxt = (r + 1) % 3;
+                __hip_atomic_store(&st->dmax[nxt], (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->xmax[nxt], (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
-            if (!bad) {
-                const TX* xin = (const TX*)((r & 1) ? S.buf0 : S.buf1);
-                TX* xout = (TX*)((r & 1) ? S.buf1 : S.buf0);
-                sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
-                                             dmax, xmax, sq);
-            }
+            const TX* xin = (const TX*)((r & 1) ? S.buf0 : S.buf1);
+            TX* xout = (TX*)((r & 1) ? S.buf1 : S.buf0);
+            sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave, dmax,
+                                         xmax, sq);
             dmax = wmax(dmax);
             xmax = wmax(xmax);
             sq = wsum(sq);
@@ -925,7 +1022,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                 red_m[wave] = xmax;
                 red_s[wave] = sq;
             }
-            __syncthreads();  // every wave's x_new stores precede tid 0's release below
+            __syncthreads();
             if (tid == 0) {
                 uint64_t D = 0, M = 0;
                 double Q = 0.0;
@@ -934,69 +1031,16 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                     M = red_m[w] > M ? red_m[w] : M;
                     Q += red_s[w];
                 }
-                if (!bad) {
-                    if (S.norm == 1)
-                        __hip_atomic_store(&p.item_parts[it], Q, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_max(&st->dmax[0], D, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_max(&st->xmax[0], M, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-                // Release only: an acquire invalidates the L2 of the XCD, which
-                // holds the iterates every item reads, so only the item that
-                // completes the system's round takes one.
-                const uint32_t t = __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_RELEASE,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                if (t + 1 == (uint32_t)(S.it1 - S.it0)) {
-                    // the last item of this system's round: the stop test
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    if (bad) {
-                        __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        D = __hip_atomic_load(&st->dmax[0], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                        M = __hip_atomic_load(&st->xmax[0], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                        if (S.norm == 1) {
-                            Q = 0.0;  // item order: independent of the schedule
-                            for (int j = S.it0; j < S.it1; ++j)
-                                Q += __hip_atomic_load(&p.item_parts[j], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                        const double delta = (S.norm == 1) ? sqrt(Q) : bitsd(D);
-                        uint32_t flag = STOP_RUNNING;
-                        if (!isfinite(delta))
-                            flag = STOP_DIVERGED;
-                        else if (S.test == TEST_ABS ? (delta < S.tol)
-                                                    : (delta <= S.rel * bitsd(M)))
-                            flag = STOP_CONVERGED;
-                        __hip_atomic_store(&st->dmax[0], (uint64_t)0, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&st->xmax[0], (uint64_t)0, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        if (flag != STOP_RUNNING || r == S.max_iter) {
-                            __hip_atomic_store(&st->status, flag, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(&st->iterations, r, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(&st->final_delta, dbits(delta), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(&st->done, r + 1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                }
+                const int slot = r % 3;
+                if (S.norm == 1)
+                    __hip_atomic_store(&p.item_parts[(size_t)par * p.nitems + it], Q,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&st->dmax[slot], D, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&st->xmax[slot], M, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        if (last) break;
         // ---- grid barrier: one release (the arrival) and one acquire per round
         if (tid == 0) {
             __hip_atomic_fetch_add(&p.ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1022,9 +1066,10 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
         }
         __syncthreads();
         if (s_abort) break;
-        // Every running system stops by its own max_iter, so the second test
-        // never decides alone; it bounds the loop whatever the counters say.
-        if (s_active == 0 || r >= p.max_rounds) last = true;
+        // Every running system is copied out by the round after its
+        // max_iter-th sweep, so the second test never decides alone; it
+        // bounds the loop whatever the counters say.
+        if (s_active == 0 || r > p.max_rounds) break;
     }
 }
 

@@ -165,16 +165,22 @@ struct alignas(64) BState {
     int64_t bad_diag;        // validation: min over bad diagonals of 2*row + (non-finite ? 1 : 0)
     int64_t bad_rhs;         // validation: first row with a non-finite B or X0 entry
     int32_t done;            // lockstep schedule: 0 running, r + 1 stopped after sweep r
-                             // (its X is copied out in round r + 1), -1 invalid input
+                             // (its X is copied out in round r + 1), -1 invalid input;
+                             // the host sets 1 for max_iter = 0 (X0 copied out in round 1)
 };
+
+constexpr int kMaxGroups = 8;  // work-item groups of the lockstep schedule (XCDs)
 
 // Grid-wide control words of the lockstep schedule (device), zeroed before
 // the launch except `active`.
 struct alignas(64) BCtl {
-    uint64_t head;    // work-item tickets handed out (all rounds)
     uint32_t bar;     // grid barrier arrivals (all rounds)
     uint32_t active;  // systems still sweeping
     uint32_t abort;   // 1: a barrier wait timed out
+    uint32_t pad;
+    // work-item tickets of each group, by round parity: round r draws from
+    // qhead[r & 1]; workgroup 0 clears the other parity during round r
+    uint32_t qhead[2][kMaxGroups];
 };
 
 struct BatchArgs {
@@ -192,11 +198,13 @@ struct BatchArgs {
     // lockstep schedule (k_rounds): one grid barrier per sweep, rows dealt
     // out as work items
     const BJob* items;        // rows [r0, r1) of system sys; `rank` unused
-    double* item_parts;       // [nitems] L2 partial sums of the current sweep
+    double* item_parts;       // [2][nitems] L2 partial sums of the sweep, by round parity
     BCtl* ctl;
+    const int32_t* group_off; // [ngroups + 1]: items of group q are [group_off[q], group_off[q+1])
+    int32_t ngroups;          // 0 (no items) .. kMaxGroups
     int32_t nitems;
     int32_t active0;          // systems with max_iter > 0
-    int32_t max_rounds;       // largest max_iter among them: no round runs past it
+    int32_t max_rounds;       // largest max_iter among them: the last round is max_rounds + 1
 };
 
 hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,

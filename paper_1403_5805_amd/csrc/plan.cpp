@@ -108,9 +108,15 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
 // About eight items per workgroup and round keeps the round's tail short (the
 // last items are the small systems'); the floor keeps the per-item ticket and
 // pipeline start small next to the item's loads.
-ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes) {
+// Grouping by XCD: all items of a system run on one XCD (while its own
+// workgroups have work), so the system's iterate, which every one of its
+// items reads in full, stays in that XCD's L2 instead of being fetched again
+// by every XCD.
+ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes,
+                    int ngroups) {
     ItemPlan p;
     const int count = (int)n.size();
+    p.ngroups = std::max(1, ngroups);
     p.it0.assign(count, 0);
     p.it1.assign(count, 0);
     double total = 0.0;
@@ -121,16 +127,31 @@ ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int el
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
-    const int64_t unit = 16 * (int64_t)tpp;
+    // largest systems first, each to the lightest group so far
+    std::vector<std::vector<int>> members(p.ngroups);
+    std::vector<double> load(p.ngroups, 0.0);
     for (int s : order) {
-        p.it0[s] = (int32_t)p.items.size();
-        if (n[s] > 0) {
-            int64_t rows = (int64_t)std::ceil(target / ((double)n[s] * elem_bytes));
-            rows = std::max<int64_t>(unit, (rows + unit - 1) / unit * unit);
-            for (int64_t r0 = 0; r0 < n[s]; r0 += rows)
-                p.items.push_back(BJob{s, 0, (int32_t)r0, (int32_t)std::min(n[s], r0 + rows)});
+        int g = 0;
+        for (int q = 1; q < p.ngroups; ++q)
+            if (load[q] < load[g]) g = q;
+        members[g].push_back(s);
+        load[g] += (double)n[s] * (double)n[s];
+    }
+    const int64_t unit = 16 * (int64_t)tpp;
+    p.g_off.push_back(0);
+    for (int g = 0; g < p.ngroups; ++g) {
+        for (int s : members[g]) {
+            p.it0[s] = (int32_t)p.items.size();
+            if (n[s] > 0) {
+                int64_t rows = (int64_t)std::ceil(target / ((double)n[s] * elem_bytes));
+                rows = std::max<int64_t>(unit, (rows + unit - 1) / unit * unit);
+                for (int64_t r0 = 0; r0 < n[s]; r0 += rows)
+                    p.items.push_back(
+                        BJob{s, 0, (int32_t)r0, (int32_t)std::min(n[s], r0 + rows)});
+            }
+            p.it1[s] = (int32_t)p.items.size();
         }
-        p.it1[s] = (int32_t)p.items.size();
+        p.g_off.push_back((int32_t)p.items.size());
     }
     p.grid = std::min<int64_t>(std::max(1, capacity), (int64_t)p.items.size());
     return p;

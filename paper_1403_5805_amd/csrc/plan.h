@@ -40,11 +40,15 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
                int max_split = 1 << 30);
 
 // Work items of the lockstep schedule: the rows of every system cut into
-// chunks (systems by decreasing n, rows in order); items of system s are
-// items[it0[s] .. it1[s]).
+// chunks (rows in order); items of system s are items[it0[s] .. it1[s]).
+// Systems are shared out among `ngroups` groups (one per XCD: workgroup g
+// runs on XCD g % ngroups), balanced by bytes of A; the items of group q are
+// items[g_off[q] .. g_off[q + 1]), its systems by decreasing n.
 struct ItemPlan {
     std::vector<BJob> items;  // rank = 0
     std::vector<int32_t> it0, it1;
+    std::vector<int32_t> g_off;  // ngroups + 1 entries
+    int ngroups = 1;
     int grid = 0;             // workgroups to launch: min(capacity, items)
 };
 
@@ -53,7 +57,9 @@ struct ItemPlan {
 // rows long except the system's last; an item holds about
 // clamp(total bytes / (capacity * 8), 128 KiB, 2 MiB) of A (elem_bytes per
 // value) or the whole system when that is smaller.  Systems with n[s] = 0
-// get an empty range.
-ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes);
+// get an empty range.  Each system's items lie inside one group; a system
+// goes to the group with the fewest bytes so far, largest systems first.
+ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes,
+                    int ngroups = 1);
 
 }  // namespace jac

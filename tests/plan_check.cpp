@@ -2,9 +2,11 @@
 // Reads "capacity tpp unroll bw count n_0 ... n_{count-1}" from stdin and
 // prints the plan: "grid G", one "nwg i v" line per system, one
 // "wg g sys rank r0 r1" line per fixed job and one "q sys" line per queue
-// entry, in queue order.  With "items capacity tpp elem_bytes count n_0 ..."
-// it prints the lockstep work items instead: "grid G", one "range s it0 it1"
-// line per system and one "item j sys r0 r1" line per item.  Built with g++;
+// entry, in queue order.  With a leading "items"
+// ("items capacity tpp elem_bytes groups count n_0 ...") it prints the
+// lockstep work items instead: "grid G", one "goff q offset" line per group
+// boundary, one "range s it0 it1" line per system and one "item j sys r0 r1"
+// line per item.  Built with g++;
 // no GPU involved.
 #include <cstdio>
 #include <cstdlib>
@@ -14,16 +16,17 @@
 #include "../paper_1403_5805_amd/csrc/plan.h"
 
 static int items_mode() {
-    int capacity, tpp, elem, count;
-    if (std::scanf("%d %d %d %d", &capacity, &tpp, &elem, &count) != 4) return 2;
+    int capacity, tpp, elem, groups, count;
+    if (std::scanf("%d %d %d %d %d", &capacity, &tpp, &elem, &groups, &count) != 5) return 2;
     std::vector<int64_t> n(count);
     for (int i = 0; i < count; ++i) {
         long long v;
         if (std::scanf("%lld", &v) != 1) return 2;
         n[i] = v;
     }
-    const jac::ItemPlan p = jac::make_items(n, capacity, tpp, elem);
+    const jac::ItemPlan p = jac::make_items(n, capacity, tpp, elem, groups);
     std::printf("grid %d\n", p.grid);
+    for (size_t g = 0; g < p.g_off.size(); ++g) std::printf("goff %zu %d\n", g, p.g_off[g]);
     for (int i = 0; i < count; ++i) std::printf("range %d %d %d\n", i, p.it0[i], p.it1[i]);
     for (size_t j = 0; j < p.items.size(); ++j)
         std::printf("item %zu %d %d %d\n", j, p.items[j].sys, p.items[j].r0, p.items[j].r1);

@@ -339,37 +339,59 @@ def test_planner_on_the_batched_workload(plan_exe):
             assert r1 - r0 >= 32 or r1 == ns[s]
 
 
-def _items(exe, ns, capacity, tpp=2, elem=4):
-    inp = f"items {capacity} {tpp} {elem} {len(ns)} " + " ".join(str(int(v)) for v in ns)
+def _items(exe, ns, capacity, tpp=2, elem=4, groups=1):
+    inp = (f"items {capacity} {tpp} {elem} {groups} {len(ns)} " +
+           " ".join(str(int(v)) for v in ns))
     out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True).stdout
-    grid, ranges, items = 0, {}, []
+    grid, ranges, items, goff = 0, {}, [], []
     for ln in out.splitlines():
         p = ln.split()
         if p[0] == "grid":
             grid = int(p[1])
+        elif p[0] == "goff":
+            assert int(p[1]) == len(goff)
+            goff.append(int(p[2]))
         elif p[0] == "range":
             ranges[int(p[1])] = (int(p[2]), int(p[3]))
         else:
             assert int(p[1]) == len(items)
             items.append(tuple(map(int, p[2:])))
-    return grid, ranges, items
+    return grid, ranges, items, goff
 
 
 def test_lockstep_items_invariants(plan_exe):
     """Work items of the lockstep schedule: each system's rows covered once,
-    in order, by a contiguous item range; chunks are whole passes of
-    16 * tpp rows except a system's last; systems by decreasing n; item
-    sizes near the target; grid = min(capacity, items)."""
+    in order, by a contiguous item range inside one group; groups partition
+    the items in order; chunks are whole passes of 16 * tpp rows except a
+    system's last; systems by decreasing n within a group; the groups' bytes
+    balanced as the largest-first greedy rule makes them; item sizes near the
+    target; grid = min(capacity, items)."""
     rng = np.random.default_rng(5805)
-    cases = [([], 512, 2, 4), ([1], 512, 2, 4), ([16384], 512, 2, 4), ([32768], 256, 4, 2),
-             ([5, 0, 7], 8, 4, 4), ([4096] * 3 + [256], 4, 2, 2)]
+    cases = [([], 512, 2, 4, 1), ([1], 512, 2, 4, 8), ([16384], 512, 2, 4, 8),
+             ([32768], 256, 4, 2, 1), ([5, 0, 7], 8, 4, 4, 8), ([4096] * 3 + [256], 4, 2, 2, 8),
+             ([4096] * 20, 256, 4, 4, 8)]
     for _ in range(30):
         count = int(rng.integers(1, 300))
         ns = np.exp(rng.uniform(np.log(1), np.log(20000), count)).astype(int)
         cases.append((list(ns), int(rng.integers(1, 1024)), int(rng.choice([2, 4])),
-                      int(rng.choice([2, 4]))))
-    for ns, cap, tpp, elem in cases:
-        grid, ranges, items = _items(plan_exe, ns, cap, tpp, elem)
+                      int(rng.choice([2, 4, 8])), int(rng.choice([1, 8]))))
+    for ns, cap, tpp, elem, groups in cases:
+        grid, ranges, items, goff = _items(plan_exe, ns, cap, tpp, elem, groups)
+        assert len(goff) == groups + 1 and goff[0] == 0 and goff[-1] == len(items)
+        assert all(a <= b for a, b in zip(goff, goff[1:]))
+        group_of = {}
+        for g in range(groups):
+            for j in range(goff[g], goff[g + 1]):
+                group_of[j] = g
+        # greedy balance: each group's load <= lightest group's load + largest system
+        loads = [0] * groups
+        for s_, (a, b) in ranges.items():
+            if b > a:
+                g = group_of[a]
+                assert all(group_of[j] == g for j in range(a, b))
+                loads[g] += int(ns[s_]) ** 2
+        if ns:
+            assert max(loads) <= min(loads) + max(int(v) for v in ns) ** 2
         assert grid == min(max(1, cap), len(items))
         total = sum(int(v) * int(v) * elem for v in ns)
         target = min(2 << 20, max(128 << 10, total / (8 * max(1, cap))))
@@ -389,8 +411,11 @@ def test_lockstep_items_invariants(plan_exe):
             assert r == n
             seen.extend(range(a, b))
         assert sorted(seen) == list(range(len(items)))
-        order = [it[0] for j, it in enumerate(items) if j == 0 or items[j - 1][0] != it[0]]
-        assert [int(ns[i]) for i in order] == sorted((int(ns[i]) for i in order), reverse=True)
+        for g in range(groups):
+            grp = items[goff[g]:goff[g + 1]]
+            order = [it[0] for j, it in enumerate(grp) if j == 0 or grp[j - 1][0] != it[0]]
+            assert [int(ns[i]) for i in order] == sorted((int(ns[i]) for i in order),
+                                                         reverse=True)
 
 
 # ---- serving arena -----------------------------------------------------------
