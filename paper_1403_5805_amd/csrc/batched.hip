@@ -858,8 +858,10 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 // the schedule): no item waits for, or fences against, the other items of
 // its system inside a round.  A system that stops after sweep r - 1 has its
 // rows copied to the caller's X by its items in round r; its first item
-// records the outcome.  The loop ends after the round in which the last
-// system is copied out.
+// records the outcome.  The loop ends after the first round in which no
+// system swept (its copies done): every workgroup reads that round's count
+// after the barrier, and nothing changes the count after the barrier, so all
+// workgroups leave after the same round.
 template <typename TA, int KT, int W, int TPW, int U, int MINB>
 __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     using TX = typename IterOf<TA>::T;
@@ -870,7 +872,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     __shared__ int32_t s_item, s_act;
     __shared__ uint32_t s_flag;
     __shared__ double s_delta;
-    __shared__ uint32_t s_active, s_abort;
+    __shared__ uint32_t s_swept, s_abort;
     enum { ACT_SKIP = 0, ACT_COPY = 1, ACT_STOP = 2, ACT_SWEEP = 3, ACT_INVALID = 4 };
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -881,6 +883,9 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
         // every workgroup has left; they are next drawn in round r + 1
         if (blockIdx.x == 0 && tid < p.ngroups)
             __hip_atomic_store(&p.ctl->qhead[par ^ 1][tid], 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (blockIdx.x == 0 && tid == 0)
+            __hip_atomic_store(&p.ctl->swept[(r + 1) % 3], 0u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         int qoff = 0;  // thread 0: groups of this round found empty, own group first
         for (;;) {
@@ -970,11 +975,8 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
             const BSys S = p.sys[item.sys];
             const bool first = it == S.it0;
             if (act == ACT_INVALID) {
-                if (first && tid == 0) {
+                if (first && tid == 0)
                     __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
                 continue;
             }
             if (act == ACT_COPY || act == ACT_STOP) {
@@ -994,8 +996,6 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                     __hip_atomic_store(&st->final_delta, dbits(s_delta), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(&st->done, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_sub(&p.ctl->active, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
                 continue;
             }
@@ -1007,6 +1007,8 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                                    __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&st->xmax[nxt], (uint64_t)0, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&p.ctl->swept[r % 3], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
@@ -1061,15 +1063,16 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_abort = abort;
-            s_active = __hip_atomic_load(&p.ctl->active, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+            s_swept = __hip_atomic_load(&p.ctl->swept[r % 3], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         if (s_abort) break;
-        // Every running system is copied out by the round after its
-        // max_iter-th sweep, so the second test never decides alone; it
-        // bounds the loop whatever the counters say.
-        if (s_active == 0 || r > p.max_rounds) break;
+        // No system swept in round r: every system has been copied out (in
+        // this round or earlier).  Every running system is copied out by the
+        // round after its max_iter-th sweep, so the second test never decides
+        // alone; it bounds the loop whatever the counters say.
+        if (s_swept == 0 || r > p.max_rounds) break;
     }
 }
 

@@ -175,9 +175,15 @@ constexpr int kMaxGroups = 8;  // work-item groups of the lockstep schedule (XCD
 // the launch except `active`.
 struct alignas(64) BCtl {
     uint32_t bar;     // grid barrier arrivals (all rounds)
-    uint32_t active;  // systems still sweeping
+    uint32_t active;  // systems with sweeps to run (set by the host)
     uint32_t abort;   // 1: a barrier wait timed out
     uint32_t pad;
+    // systems that swept in round r, in swept[r % 3]: read by every
+    // workgroup after the round's barrier (the loop ends when it is zero);
+    // workgroup 0 clears swept[(r + 1) % 3] during round r, when every
+    // workgroup has read it
+    uint32_t swept[3];
+    uint32_t pad2;
     // work-item tickets of each group, by round parity: round r draws from
     // qhead[r & 1]; workgroup 0 clears the other parity during round r
     uint32_t qhead[2][kMaxGroups];

@@ -10,6 +10,10 @@ Workload presets (one per measured configuration):
 * ``C4``  FP64 n=32768, multiplicative margin U[0.5,1], stored BF16 for sweeps
 * ``C5``  2000 requests, n log-uniform in [256, 16384], k in {1,4,16},
   multiplicative margin U[0.2,1], Poisson arrivals
+* ``C4S`` FP64 n=32768 with non-negative off-diagonals U[0,1] (the paper's
+  sign pattern) and a_ii = 1.05 rowsum: a slowly converging system
+* ``REPLAY`` FP64 systems of the sizes of the paper's serial timing table
+  (n = 8 ... 512), additive margin U[1,2]
 """
 from __future__ import annotations
 
@@ -26,6 +30,7 @@ LIB = os.path.join(HERE, "libsynth.so")
 SEED_BASE = 0x14035805
 ADDITIVE = 0
 MULTIPLICATIVE = 1
+NONNEGATIVE = 2  # off-diagonals U[0,1], multiplicative margin
 
 
 def seed_for(config_index: int) -> int:
@@ -166,6 +171,20 @@ def c3_system(i: int, n: int, k: int = 32):
 def c4(n: int = 32768):
     """FP64 n=32768, multiplicative margin U[0.5,1] (swept in BF16)."""
     return dominant(n, 1, seed_for(3), MULTIPLICATIVE, 0.5, 1.0)
+
+
+def c4_slow(n: int = 32768):
+    """FP64 n=32768, off-diagonals U[0,1], a_ii = 1.05 rowsum (spectral radius
+    of the Jacobi matrix 1/1.05)."""
+    return dominant(n, 1, seed_for(5), NONNEGATIVE, 0.05, 0.05)
+
+
+REPLAY_SIZES = (8, 16, 32, 64, 128, 256, 512)
+
+
+def replay_system(n: int):
+    """FP64 system of one size of the paper's serial timing table."""
+    return dominant(n, 1, seed_for(6) * 1000003 + n, ADDITIVE, 1.0, 2.0)
 
 
 C5_STREAM_K = 9

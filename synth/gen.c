@@ -16,6 +16,11 @@
  *     rowsum_i * (1 + U[lo,hi]) (multiplicative margin), which makes A
  *     strictly diagonally dominant (the paper's sufficient condition, sec. 2);
  *     X_true iid U[-1,1]; B = A X_true summed in FP64, j ascending.
+ *     Mode 2 draws the off-diagonals iid U[0,1] instead (the sign pattern of
+ *     the paper's experiments, sec. 4) with the multiplicative margin: with
+ *     a_ii = 1.05 rowsum_i every row of |D^-1 (A - D)| sums to 1/1.05, so the
+ *     Jacobi matrix has spectral radius 0.952 and the iteration converges
+ *     slowly (hundreds of sweeps to 1e-10).
  *   synth_paper_uniform: A, B and X iid U[0,1], as in the paper's experiments
  *     (sec. 4); such matrices are not diagonally dominant.
  */
@@ -69,8 +74,13 @@ static double synth_diag(double rowsum, uint64_t km, int64_t i, int32_t mode, do
     return mode == 0 ? rowsum + u : rowsum * (1.0 + u);
 }
 
+static inline double synth_offdiag(uint64_t ka, uint64_t idx, int32_t mode) {
+    return mode == 2 ? synth_range(ka, idx, 0.0, 1.0) : synth_range(ka, idx, -1.0, 1.0);
+}
+
 /* FP64 system.  A is n x lda (row-major), X_true and B are n x k contiguous.
- * mode 0: additive margin, mode 1: multiplicative margin. */
+ * mode 0: additive margin, mode 1: multiplicative margin, mode 2:
+ * non-negative off-diagonals with the multiplicative margin. */
 void synth_dominant(int64_t n, int64_t k, uint64_t seed, int32_t mode, double lo, double hi,
                     double* A, int64_t lda, double* Xtrue, double* B) {
     uint64_t ka = synth_key(seed, STREAM_OFFDIAG);
@@ -82,7 +92,7 @@ void synth_dominant(int64_t n, int64_t k, uint64_t seed, int32_t mode, double lo
         double rowsum = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            double a = synth_range(ka, (uint64_t)(i * n + j), -1.0, 1.0);
+            double a = synth_offdiag(ka, (uint64_t)(i * n + j), mode);
             row[j] = a;
             rowsum += fabs(a);
         }
@@ -108,7 +118,7 @@ void synth_dominant_f32(int64_t n, int64_t k, uint64_t seed, int32_t mode, doubl
         double rowsum = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            double a = synth_range(ka, (uint64_t)(i * n + j), -1.0, 1.0);
+            double a = synth_offdiag(ka, (uint64_t)(i * n + j), mode);
             row[j] = (float)a;
             rowsum += fabs(a);
         }

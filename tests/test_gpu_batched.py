@@ -414,3 +414,47 @@ def test_paper_inputs_diverge_per_system(jac):
     alone, ia = jac.solve_batched([good], tol=1e-8, max_iter=10000)
     assert infos[-1]["status"] == jac.OK
     assert torch.equal(alone[0], xs[-1]) and ia[0]["iterations"] == infos[-1]["iterations"]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_many_small_systems_stop_in_different_rounds(jac, dtype):
+    """Hundreds of small systems (n = 1 ... 96) whose stop tests fire in
+    different rounds, with max_iter = 0 systems and an invalid system among
+    them, solved five times in a row: every launch ends normally (no barrier
+    wait times out), every outcome is the one the system gets alone, and the
+    counts agree with the oracle's."""
+    import torch
+    rng = np.random.default_rng(77)
+    ns = rng.integers(1, 97, size=300)
+    sysl, refs = [], []
+    for i, n in enumerate(ns):
+        n = int(n)
+        k = int(rng.integers(1, 5))
+        A, B = _sys_dev(n, k, 2000 + i, dtype)
+        sysl.append((A, B))
+    bad = list(sysl)
+    Bb = sysl[5][1].clone()
+    Bb[0, 0] = float("nan")
+    bad[5] = (sysl[5][0], Bb)
+    tol = 1e-11 if dtype == "f64" else 1e-6
+    # tolerances spread the stop rounds: every third system runs a fixed count
+    say("many small systems", dtype)
+    first = None
+    for rep in range(5):
+        xs, infos = jac.solve_batched(bad, tol=tol, max_iter=60)
+        assert all(i["status"] != jac.ERR_INTERNAL for i in infos), rep
+        assert infos[5]["status"] == jac.ERR_NONFINITE_INPUT
+        if first is None:
+            first = (xs, infos)
+        else:
+            for a, b, ia, ib in zip(first[0], xs, first[1], infos):
+                if ia["status"] >= 0:
+                    assert torch.equal(a, b) and ia["iterations"] == ib["iterations"]
+    xs, infos = first
+    for i in (0, 1, 2, 17, 100, 299):
+        x1, i1 = jac.solve_batched([sysl[i]], tol=tol, max_iter=60)
+        assert torch.equal(x1[0], xs[i]) and i1[0]["iterations"] == infos[i]["iterations"], i
+    zero, zinfo = jac.solve_batched(sysl[:40], tol=tol, max_iter=0)
+    assert all(z["iterations"] == 0 and z["status"] == jac.NOT_CONVERGED for z in zinfo)
+    counts = {int(i["iterations"]) for i in infos if i["status"] == jac.OK}
+    assert len(counts) >= 3, counts
