@@ -104,9 +104,10 @@ typedef struct {
     int32_t status;           /* jacobi_status of this system                            */
     int32_t iterations;       /* sweeps executed (REFINE: inner sweeps, all corrections)  */
     int32_t outer_iterations; /* REFINE: residual evaluations; PLAIN: 0                  */
-    int32_t kernel;           /* batched FP32/BF16 systems: 1 = lockstep schedule, plus 2 =
-                                 deep shape (one workgroup per CU); 0 = planned schedule,
-                                 wide shape, or not a batched-kernel solve                 */
+    int32_t kernel;           /* batched-kernel solves: bit 0 lockstep schedule (else
+                                 planned), bit 1 deep shape (one workgroup per CU, else two),
+                                 bits 2-4 XCD groups - 1 and bits 8+ work items per
+                                 workgroup (lockstep); 0 for other solves                   */
     int64_t bad_index;        /* first offending row for ZERO_DIAGONAL / NONFINITE, or -1 */
     double final_delta;       /* distance of the last executed sweep (-1 if none)        */
     double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */

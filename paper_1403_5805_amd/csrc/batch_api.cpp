@@ -9,7 +9,10 @@
 #include <cstring>
 #include <numeric>
 #include <queue>
+#include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "batch.h"
 #include "ctx.h"
@@ -80,7 +83,8 @@ static void decode_states(const BState* hst, int32_t count, float ms, int32_t ke
 static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const BatchItem* items,
                                        int32_t a_dtype, const jacobi_options& o, int32_t test,
                                        double rel, hipStream_t s, jacobi_info* infos,
-                                       int variant, int sched) {
+                                       const BatchTune& tune) {
+    const int variant = tune.shape, sched = tune.sched;
     int kmax = 1;
     int64_t nmax = 1;
     for (int i = 0; i < count; ++i) {
@@ -103,10 +107,8 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     const size_t ea = a_dtype == JACOBI_F64 ? 8 : (a_dtype == JACOBI_F32 ? 4 : 2);
     const size_t ex = a_dtype == JACOBI_F64 ? 8 : 4;  // iterate element
     if (sched == 1) {
-        int groups = 1;  // JACOBI_BATCHED_GROUPS=8 groups the items by XCD
-        if (const char* env = getenv("JACOBI_BATCHED_GROUPS"))
-            groups = std::min(kMaxGroups, std::max(1, atoi(env)));
-        ip = make_items(ns, capacity, tpp, (int)ea, groups);
+        ip = make_items(ns, capacity, tpp, (int)ea, std::min(kMaxGroups, std::max(1, tune.groups)),
+                        tune.per_wg);
         grid = ip.grid;
     } else {
         int max_split = 1 << 30;
@@ -272,30 +274,103 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     }
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
-    decode_states(hst.data(), count, ms, (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0), infos);
+    decode_states(hst.data(), count, ms,
+                  (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0) |
+                      (sched == 1 ? (std::min(tune.groups, kMaxGroups) - 1) << 2 : 0) |
+                      (sched == 1 ? tune.per_wg << 8 : 0),
+                  infos);
     return JACOBI_OK;
 }
 
-// Kernel shape for a batch: JACOBI_BATCHED_SHAPE when set; else the shape
-// measured fastest for batches of this class (element type, output width and
-// power-of-two buckets of the system count, largest n and bytes per sweep),
-// found by solving the batch on both shapes the first time the class is seen.
-// Both shapes give bitwise the same results, so the choice only affects
-// speed.  Batches too small to be worth a trial, and batches
-// whose initial approximation aliases the output (a trial would overwrite
-// it), use the rule of thumb: wide for many systems, deep for few.
+// ---------------------------------------------------------------------------
+// Tuning.  Every variant of a batched launch -- schedule (lockstep or planned),
+// kernel shape (wide or deep), XCD grouping and items per workgroup of the
+// lockstep schedule -- sums every element in the same order, so all of them
+// give bitwise the same X, counts and maximum-norm distances (tested); only
+// the time differs.  The first batch of a class (schedule choice, element
+// type, output width, and the power-of-two classes of system count, largest
+// n and bytes of A) that is worth it is therefore solved several times, once
+// per candidate, each run being the solve itself, and the fastest candidate
+// is kept: in the context for its life, and in a cache file (one per GPU
+// architecture, HIP runtime and library build) that later processes read.
+// The search is staged: schedule x shape first, then for the lockstep
+// schedule the XCD grouping and the items per workgroup, one at a time.
+// Environment overrides: JACOBI_BATCHED_SCHED (lockstep | planned),
+// JACOBI_BATCHED_SHAPE (wide | deep), JACOBI_BATCHED_GROUPS (1..8),
+// JACOBI_BATCHED_ITEMS (items per workgroup), JACOBI_TUNE (auto | off |
+// always), JACOBI_TUNE_CACHE (file path, or "off").
+
+namespace {
+
+// Build stamp of this library: cached choices of another build are ignored.
+const char* const kBuildStamp = __DATE__ " " __TIME__;
+
+std::mutex g_tune_file_mu;
+
+std::string tune_cache_path(int device) {
+    const char* env = getenv("JACOBI_TUNE_CACHE");
+    if (env && !strcmp(env, "off")) return "";
+    if (env && *env) return env;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "";
+    int rt = 0;
+    hipRuntimeGetVersion(&rt);
+    std::string arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ':' || ch == '/' || ch == ' ') ch = '_';
+    const char* home = getenv("HOME");
+    const char* xdg = getenv("XDG_CACHE_HOME");
+    std::string dir = xdg && *xdg ? std::string(xdg) : (home ? std::string(home) + "/.cache" : "");
+    if (dir.empty()) return "";
+    return dir + "/libjacobi-tune-" + arch + "-hip" + std::to_string(rt) + ".txt";
+}
+
+// Entries of the cache file written by this build: "stamp|key shape sched groups per_wg".
+void tune_cache_load(jacobi_ctx* c) {
+    if (c->tune_loaded) return;
+    c->tune_loaded = true;
+    c->tune_path = tune_cache_path(c->device);
+    if (c->tune_path.empty()) return;
+    std::lock_guard<std::mutex> g(g_tune_file_mu);
+    FILE* f = fopen(c->tune_path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof(line), f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (strcmp(line, kBuildStamp) != 0) continue;
+        unsigned long long key = 0;
+        BatchTune t;
+        if (sscanf(bar + 1, "%llu %d %d %d %d", &key, &t.shape, &t.sched, &t.groups,
+                   &t.per_wg) == 5)
+            c->batched_tune[(uint64_t)key] = t;
+    }
+    fclose(f);
+}
+
+void tune_cache_store(jacobi_ctx* c, uint64_t key, const BatchTune& t) {
+    if (c->tune_path.empty()) return;
+    std::lock_guard<std::mutex> g(g_tune_file_mu);
+    const size_t slash = c->tune_path.rfind('/');
+    if (slash != std::string::npos) mkdir(c->tune_path.substr(0, slash).c_str(), 0755);
+    FILE* f = fopen(c->tune_path.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%s|%llu %d %d %d %d\n", kBuildStamp, (unsigned long long)key, t.shape, t.sched,
+            t.groups, t.per_wg);
+    fclose(f);
+}
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+}  // namespace
+
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
                           const jacobi_options& o, int32_t test, double rel, hipStream_t s,
                           jacobi_info* infos) {
-    int sched = 1;  // JACOBI_BATCHED_SCHED=planned selects the planned schedule
-    if (const char* env = getenv("JACOBI_BATCHED_SCHED"))
-        if (!strcmp(env, "planned")) sched = 0;
-    if (const char* env = getenv("JACOBI_BATCHED_SHAPE")) {
-        const int forced = !strcmp(env, "wide") ? 0 : (!strcmp(env, "deep") ? 1 : -1);
-        if (forced >= 0)
-            return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, forced,
-                                     sched);
-    }
     int kmax = 1;
     int64_t nmax = 1;
     double bytes = 0.0;
@@ -307,7 +382,30 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
                  (a_dtype == JACOBI_F64 ? 8.0 : (a_dtype == JACOBI_F32 ? 4.0 : 2.0));
         if (items[i].X0 && items[i].X0 == items[i].X) alias = true;
     }
-    const int rule = count * 4 >= c->num_cus ? 0 : 1;
+    // The rule of thumb when nothing is measured: lockstep; wide for many
+    // systems, deep for few; no grouping; eight items per workgroup.
+    BatchTune rule;
+    rule.sched = 1;
+    rule.shape = count * 4 >= c->num_cus ? 0 : 1;
+    rule.groups = 1;
+    rule.per_wg = 8;
+    // Overrides fix a parameter and keep it out of the search.
+    int f_sched = -1, f_shape = -1;
+    if (const char* env = getenv("JACOBI_BATCHED_SCHED"))
+        f_sched = !strcmp(env, "planned") ? 0 : (!strcmp(env, "lockstep") ? 1 : -1);
+    if (const char* env = getenv("JACOBI_BATCHED_SHAPE"))
+        f_shape = !strcmp(env, "wide") ? 0 : (!strcmp(env, "deep") ? 1 : -1);
+    const int f_groups = env_int("JACOBI_BATCHED_GROUPS", -1);
+    const int f_items = env_int("JACOBI_BATCHED_ITEMS", -1);
+    auto apply = [&](BatchTune t) {
+        if (f_sched >= 0) t.sched = f_sched;
+        if (f_shape >= 0) t.shape = f_shape;
+        if (f_groups >= 1) t.groups = f_groups;
+        if (f_items >= 1) t.per_wg = f_items;
+        return t;
+    };
+    const char* tenv = getenv("JACOBI_TUNE");
+    const int mode = tenv && !strcmp(tenv, "off") ? 0 : (tenv && !strcmp(tenv, "always") ? 2 : 1);
     auto lg = [](double v) {
         int b = 0;
         while (v >= 2.0 && b < 62) {
@@ -316,57 +414,96 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         }
         return (uint64_t)b;
     };
-    const uint64_t key = ((uint64_t)sched << 60) | ((uint64_t)a_dtype << 56) |
+    const uint64_t key = ((uint64_t)(f_sched + 1) << 60) | ((uint64_t)a_dtype << 56) |
                          ((uint64_t)(kmax <= 16 ? 16 : 32) << 48) | (lg(count) << 32) |
                          (lg((double)nmax) << 16) | lg(bytes);
-    auto hit = c->batched_shape.find(key);
-    if (hit != c->batched_shape.end())
-        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, hit->second,
-                                 sched);
-    if (alias || bytes < 32.0 * 1024 * 1024 || o.max_iter < 2)
-        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, rule, sched);
-    // Both shapes give the same X and outcomes, so the two timed runs are the
-    // solve itself: the first call of a class costs one extra solve.  An
-    // empty launch of each shape first takes the one-time cost of a kernel's
-    // first launch out of the comparison.
+    // Worth a search: at least about 32 MiB of sweeps expected (bytes of A
+    // times the sweeps the cap allows, up to 64).
+    const double work = bytes * (double)std::min(o.max_iter, 64);
+    const bool tune = mode == 2 || (mode == 1 && !alias && o.max_iter >= 2 &&
+                                    work >= 32.0 * 1024 * 1024 && count > 0);
+    if (mode != 0) tune_cache_load(c);
+    auto hit = c->batched_tune.find(key);
+    if (mode != 0 && hit != c->batched_tune.end() && mode != 2)
+        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos,
+                                 apply(hit->second));
+    if (!tune)
+        return run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, apply(rule));
+    // Warm-up: an empty launch of each kernel shape takes the one-time cost of
+    // a kernel's first launch out of the comparison.
     {
         const int kt = kmax <= 16 ? 16 : 32;
         HIP_TRY(c->warm.ensure(256));
-        int32_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int32_t zeros[16] = {0};
         HIP_TRY(c->stage.ensure(sizeof(zeros)));
         std::memcpy(c->stage.h, zeros, sizeof(zeros));
         HIP_TRY(launch_copy16(c->stage.d, c->warm.p, sizeof(zeros), s));
-        BatchArgs wa{};
-        if (sched == 1) {
-            wa.ctl = (BCtl*)c->warm.p;  // no item, no active system: one copy-only round
-            wa.nitems = 0;
-            wa.active0 = 0;
-            for (int v = 0; v < 2; ++v) HIP_TRY(launch_rounds(a_dtype, kt, v, wa, 1, s));
-        } else {
-            wa.job_off = (const int32_t*)c->warm.p;  // one workgroup, no fixed job
-            wa.queue_head = (uint32_t*)((char*)c->warm.p + 16);
-            wa.queue = (const int32_t*)c->warm.p;
-            wa.queue_len = 0;  // and an empty queue
-            for (int v = 0; v < 2; ++v) HIP_TRY(launch_batched(a_dtype, kt, v, wa, 1, s));
+        for (int v = 0; v < 2; ++v) {
+            BatchArgs wa{};
+            wa.ctl = (BCtl*)c->warm.p;  // no item, no system: one empty round
+            HIP_TRY(launch_rounds(a_dtype, kt, v, wa, 1, s));
+            BatchArgs wb{};
+            wb.job_off = (const int32_t*)c->warm.p;  // one workgroup, no fixed job
+            wb.queue_head = (uint32_t*)((char*)c->warm.p + 16);
+            wb.queue = (const int32_t*)c->warm.p;
+            wb.queue_len = 0;  // and an empty queue
+            HIP_TRY(launch_batched(a_dtype, kt, v, wb, 1, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
     }
-    // The other shape runs first: what still favours a later run (caches,
-    // translations) then favours the rule's shape, which stays unless the
-    // other one is faster all the same.
-    const int order[2] = {1 - rule, rule};
-    double ms[2] = {0.0, 0.0};
-    for (int t = 0; t < 2; ++t) {
-        jacobi_status st =
-            run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, order[t], sched);
+    const bool trace = getenv("JACOBI_BATCHED_TRACE") != nullptr;
+    BatchTune best{};
+    double best_ms = 1e300;
+    auto trial = [&](BatchTune t) -> jacobi_status {
+        t = apply(t);
+        jacobi_status st = run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, t);
         if (st != JACOBI_OK) return st;
-        ms[t] = count > 0 ? infos[0].device_ms : 0.0;
+        const double ms = infos[0].device_ms;
+        if (trace)
+            std::fprintf(stderr, "jacobi tune: %s %s groups %d items %d: %.3f ms\n",
+                         t.sched ? "lockstep" : "planned", t.shape ? "deep" : "wide", t.groups,
+                         t.per_wg, ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+        return JACOBI_OK;
+    };
+    // stage 1: schedule x shape (the rule's candidate last, so that whatever
+    // still favours a later run favours the default)
+    std::vector<BatchTune> stage1;
+    for (int sc : {0, 1})
+        for (int sh : {0, 1}) {
+            BatchTune t = rule;
+            t.sched = sc;
+            t.shape = sh;
+            if (!(sc == rule.sched && sh == rule.shape)) stage1.push_back(t);
+        }
+    stage1.push_back(rule);
+    for (const BatchTune& t : stage1) {
+        if ((f_sched >= 0 && t.sched != f_sched) || (f_shape >= 0 && t.shape != f_shape))
+            continue;
+        jacobi_status st = trial(t);
+        if (st != JACOBI_OK) return st;
     }
-    c->batched_shape[key] = ms[0] < ms[1] ? order[0] : rule;
-    if (std::getenv("JACOBI_BATCHED_TRACE"))
-        std::fprintf(stderr, "jacobi batched shape trial: %s %.3f ms, %s %.3f ms -> %s\n",
-                     order[0] ? "deep" : "wide", ms[0], order[1] ? "deep" : "wide", ms[1],
-                     c->batched_shape[key] ? "deep" : "wide");
+    // stage 2: the lockstep schedule's grouping and item size
+    if (best.sched == 1) {
+        if (f_groups < 1) {
+            BatchTune t = best;
+            t.groups = kMaxGroups;
+            jacobi_status st = trial(t);
+            if (st != JACOBI_OK) return st;
+        }
+        if (f_items < 1)
+            for (int m : {4, 16}) {
+                BatchTune t = best;
+                t.per_wg = m;
+                jacobi_status st = trial(t);
+                if (st != JACOBI_OK) return st;
+            }
+    }
+    c->batched_tune[key] = best;
+    tune_cache_store(c, key, best);
     return JACOBI_OK;
 }
 

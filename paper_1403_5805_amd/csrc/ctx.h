@@ -21,6 +21,14 @@ struct DevBuf {
     void release();
 };
 
+// Variant of a batched launch; every variant gives bitwise the same results.
+struct BatchTune {
+    int shape = 1;   // 0 wide (two workgroups per CU), 1 deep (one)
+    int sched = 1;   // 0 planned, 1 lockstep
+    int groups = 1;  // lockstep: XCD groups of work items (1 = none)
+    int per_wg = 8;  // lockstep: work items per workgroup and round
+};
+
 // Grow-only pinned, device-mapped host buffer for the small per-call
 // descriptor uploads and outcome read-backs.  They are moved by a copy kernel
 // on the caller's stream rather than by the DMA engines, so they never queue
@@ -56,9 +64,11 @@ struct jacobi_ctx {
     jac::DevBuf rmeta, xT;
     // staging for descriptor uploads and outcome read-backs
     jac::HostStage stage;
-    // batched kernel shape measured fastest per class of batch; `warm` holds
-    // the empty job table of the warm-up launches
-    std::map<uint64_t, int> batched_shape;
+    // batched launch variant measured fastest per class of batch (also kept
+    // in a cache file); `warm` holds the empty tables of the warm-up launches
+    std::map<uint64_t, jac::BatchTune> batched_tune;
+    bool tune_loaded = false;
+    std::string tune_path;
     jac::DevBuf warm;
 };
 

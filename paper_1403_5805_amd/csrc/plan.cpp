@@ -105,15 +105,16 @@ Plan make_plan(const std::vector<int64_t>& n, int capacity, int tpp, int unroll,
     return p;
 }
 
-// About eight items per workgroup and round keeps the round's tail short (the
-// last items are the small systems'); the floor keeps the per-item ticket and
-// pipeline start small next to the item's loads.
+// About eight items per workgroup and round (per_wg, tuned per batch class)
+// keeps the round's tail short (the last items are the small systems'); the
+// floor keeps the per-item ticket and pipeline start small next to the item's
+// loads.
 // Grouping by XCD: all items of a system run on one XCD (while its own
 // workgroups have work), so the system's iterate, which every one of its
 // items reads in full, stays in that XCD's L2 instead of being fetched again
 // by every XCD.
 ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes,
-                    int ngroups) {
+                    int ngroups, int per_wg) {
     ItemPlan p;
     const int count = (int)n.size();
     p.ngroups = std::max(1, ngroups);
@@ -123,7 +124,8 @@ ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int el
     for (int64_t v : n) total += (double)v * (double)v * elem_bytes;
     const double target =
         std::min(2.0 * 1024 * 1024,
-                 std::max(128.0 * 1024, total / (8.0 * std::max(1, capacity))));
+                 std::max(128.0 * 1024,
+                          total / ((double)std::max(1, per_wg) * std::max(1, capacity))));
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });

@@ -55,11 +55,11 @@ struct ItemPlan {
 // Guarantees: every system with n[s] >= 1 has at least one item; its items
 // cover rows [0, n[s]) exactly once, in order, each a multiple of 16 * tpp
 // rows long except the system's last; an item holds about
-// clamp(total bytes / (capacity * 8), 128 KiB, 2 MiB) of A (elem_bytes per
-// value) or the whole system when that is smaller.  Systems with n[s] = 0
+// clamp(total bytes / (capacity * per_wg), 128 KiB, 2 MiB) of A (elem_bytes
+// per value) or the whole system when that is smaller.  Systems with n[s] = 0
 // get an empty range.  Each system's items lie inside one group; a system
 // goes to the group with the fewest bytes so far, largest systems first.
 ItemPlan make_items(const std::vector<int64_t>& n, int capacity, int tpp, int elem_bytes,
-                    int ngroups = 1);
+                    int ngroups = 1, int per_wg = 8);
 
 }  // namespace jac
