@@ -354,13 +354,13 @@ def bench_c1(args):
 
 def _batched_kernel_name(code: int, ta: str, kt: int) -> str:
     """Kernel that ran a batched solve, from jacobi_info.kernel (bit 0:
-    lockstep schedule, bit 1: deep shape, bits 2-4: XCD groups - 1, bits 8+:
-    items per workgroup) and its template shape."""
+    lockstep schedule, bit 1: deep shape, bits 2-4: XCD groups - 1, bits 8-15:
+    items per workgroup, bits 16+: column chunks) and its template shape."""
     deep = bool(code & 2)
     tpw = 4 if (deep or (kt <= 16 and ta == "float")) else 2
     name = "k_rounds" if code & 1 else "k_batched"
-    extra = (f"; {((code >> 2) & 7) + 1} XCD group(s), {code >> 8} items per workgroup"
-             if code & 1 else "")
+    extra = (f"; {((code >> 2) & 7) + 1} XCD group(s), {(code >> 8) & 0xff} items per "
+             f"workgroup, {max(1, code >> 16)} column chunk(s)" if code & 1 else "")
     return (f"{name}<{ta},KT={kt},W=4,TPW={tpw},U=1> ({'deep, 1' if deep else 'wide, 2'} "
             f"workgroup(s) per CU; {'lockstep' if code & 1 else 'planned'} schedule{extra})")
 

@@ -106,8 +106,9 @@ typedef struct {
     int32_t outer_iterations; /* REFINE: residual evaluations; PLAIN: 0                  */
     int32_t kernel;           /* batched-kernel solves: bit 0 lockstep schedule (else
                                  planned), bit 1 deep shape (one workgroup per CU, else two),
-                                 bits 2-4 XCD groups - 1 and bits 8+ work items per
-                                 workgroup (lockstep); 0 for other solves                   */
+                                 bits 2-4 XCD groups - 1, bits 8-15 work items per
+                                 workgroup (lockstep), bits 16+ column chunks of a split
+                                 single system (1 = none); 0 for other solves               */
     int64_t bad_index;        /* first offending row for ZERO_DIAGONAL / NONFINITE, or -1 */
     double final_delta;       /* distance of the last executed sweep (-1 if none)        */
     double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */

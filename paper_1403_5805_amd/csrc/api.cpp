@@ -310,7 +310,7 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
     // 3.0, BF16 1.4 against 4.9, 4.3 and 3.4 on the tiles).
     if (k >= mfma_min_cols(a_dtype) && k <= 32 && o.profile == 0) {
         BatchItem it{n, k, A, lda, B, ldb, X0, X, ldx, o.max_iter};
-        jacobi_status st = run_batched(c, 1, &it, a_dtype, o, TEST_ABS, 0.0, s, info);
+        jacobi_status st = run_batched(c, 1, &it, a_dtype, o, TEST_ABS, 0.0, s, info, true);
         if (st != JACOBI_OK) return st;
         if (info->status < 0 && info->status != JACOBI_ERR_INTERNAL)
             set_error("input validation failed at row %lld", (long long)info->bad_index);

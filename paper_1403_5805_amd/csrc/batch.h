@@ -21,9 +21,13 @@ struct BatchItem {
     int32_t max_iter;
 };
 
+// allow_split: a single system may have its columns split over workgroups
+// (its arithmetic then depends on the chunk count the tuner picks, so the
+// batched and served paths, whose results must not depend on the batch,
+// leave it off).
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
                           const jacobi_options& o, int32_t test, double rel, hipStream_t s,
-                          jacobi_info* infos);
+                          jacobi_info* infos, bool allow_split = false);
 
 jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_dtype,
                                  const void* A, int64_t lda, const void* B, int64_t ldb,

@@ -92,7 +92,8 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         nmax = std::max(nmax, items[i].n);
     }
     const int kt = kmax <= 16 ? 16 : 32;
-    const int capacity = sched == 1 ? rounds_max_grid(a_dtype, kt, variant, c->num_cus)
+    const bool split = sched == 1 && count == 1 && tune.csplit > 1;
+    const int capacity = sched == 1 ? rounds_max_grid(a_dtype, kt, variant, c->num_cus, split)
                                     : batched_max_grid(a_dtype, kt, variant, c->num_cus);
     if (capacity < 1) {
         set_error("batched kernel unavailable for this dtype");
@@ -106,7 +107,29 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     int grid = 0;
     const size_t ea = a_dtype == JACOBI_F64 ? 8 : (a_dtype == JACOBI_F32 ? 4 : 2);
     const size_t ex = a_dtype == JACOBI_F64 ? 8 : 4;  // iterate element
-    if (sched == 1) {
+    // Column split (one system, lockstep): chunks of cw columns, a multiple of
+    // the workgroup's block span, rows in ranges of 64 (whole passes in both
+    // kernel shapes); items range-major, chunk index in `rank`.
+    int32_t csplit = 1;
+    int64_t cw = 0;
+    if (sched == 1 && count == 1 && tune.csplit > 1) {
+        const int64_t span = batched_block_cols(a_dtype);
+        const int64_t n0 = items[0].n;
+        cw = ((n0 + tune.csplit - 1) / tune.csplit + span - 1) / span * span;
+        csplit = (int32_t)((n0 + cw - 1) / cw);
+    }
+    if (csplit > 1) {
+        const int64_t n0 = items[0].n;
+        ip.ngroups = 1;
+        ip.it0.assign(1, 0);
+        for (int64_t r0 = 0; r0 < n0; r0 += 64)
+            for (int32_t ch = 0; ch < csplit; ++ch)
+                ip.items.push_back(BJob{0, ch, (int32_t)r0, (int32_t)std::min<int64_t>(n0, r0 + 64)});
+        ip.it1.assign(1, (int32_t)ip.items.size());
+        ip.g_off = {0, (int32_t)ip.items.size()};
+        ip.grid = std::min<int>(capacity, (int)ip.items.size());
+        grid = ip.grid;
+    } else if (sched == 1) {
         ip = make_items(ns, capacity, tpp, (int)ea, std::min(kMaxGroups, std::max(1, tune.groups)),
                         tune.per_wg);
         grid = ip.grid;
@@ -132,6 +155,8 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         off[i] = ws;
         ws += 3 * align(ex * xld_of(items[i].n) * kt) + align(ex * items[i].n);
     }
+    const size_t part_off = ws;  // split: csplit chunks of partial sums (kt x xld each)
+    if (csplit > 1) ws += align(ex * (size_t)csplit * kt * xld_of(items[0].n));
     // device metadata: [sys | st | schedule tables (uploaded) | partial sums]
     //   sched 0 tables: jobs | job_off | queue head (16 bytes) + queue
     //   sched 1 tables: items | group offsets | BCtl
@@ -139,7 +164,9 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     size_t job_b = 0, off_b = 0, q_b = 0, parts_b = 0;
     if (sched == 1) {
         job_b = align(sizeof(BJob) * std::max<size_t>(1, ip.items.size()));
-        off_b = align(sizeof(int32_t) * ip.g_off.size());
+        // group offsets, then the row-range counters of a split system
+        off_b = align(sizeof(int32_t) * ip.g_off.size() +
+                      sizeof(uint32_t) * std::max<size_t>(1, ip.items.size()));
         q_b = align(sizeof(BCtl));
         parts_b = align(sizeof(double) * 2 * std::max<size_t>(1, ip.items.size()));
     } else {
@@ -181,10 +208,16 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         S.diag = base + 3 * xb;
         S.n = it.n;
         S.k = (int32_t)it.k;
+        S.csplit = 1;
         if (sched == 1) {
             S.nwg = 1;
             S.it0 = ip.it0[i];
             S.it1 = ip.it1[i];
+            if (csplit > 1) {
+                S.csplit = csplit;
+                S.cw = cw;
+                S.part = (char*)c->bws.p + part_off;
+            }
         } else {
             S.nwg = plan.nwg[i];
         }
@@ -215,6 +248,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     char* ht = h + sys_b + st_b;
     if (sched == 1) {
         std::memcpy(ht, ip.items.data(), sizeof(BJob) * ip.items.size());
+        std::memset(ht + job_b, 0, off_b);
         std::memcpy(ht + job_b, ip.g_off.data(), sizeof(int32_t) * ip.g_off.size());
         BCtl ctl;
         std::memset(&ctl, 0, sizeof(ctl));
@@ -246,11 +280,12 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         ba.item_parts = d_parts;
         ba.ctl = (BCtl*)d_q;
         ba.group_off = d_off;
+        ba.rcnt = (uint32_t*)((char*)d_off + sizeof(int32_t) * ip.g_off.size());
         ba.ngroups = ip.ngroups;
         ba.nitems = (int32_t)ip.items.size();
         ba.active0 = active0;
         ba.max_rounds = max_rounds;
-        if (grid > 0) HIP_TRY(launch_rounds(a_dtype, kt, variant, ba, grid, s));
+        if (grid > 0) HIP_TRY(launch_rounds(a_dtype, kt, variant, ba, grid, s, csplit > 1));
     } else {
         ba.jobs = d_jobs;
         ba.job_off = d_off;
@@ -277,7 +312,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     decode_states(hst.data(), count, ms,
                   (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0) |
                       (sched == 1 ? (std::min(tune.groups, kMaxGroups) - 1) << 2 : 0) |
-                      (sched == 1 ? tune.per_wg << 8 : 0),
+                      (sched == 1 ? tune.per_wg << 8 : 0) | (csplit << 16),
                   infos);
     return JACOBI_OK;
 }
@@ -325,7 +360,8 @@ std::string tune_cache_path(int device) {
     return dir + "/libjacobi-tune-" + arch + "-hip" + std::to_string(rt) + ".txt";
 }
 
-// Entries of the cache file written by this build: "stamp|key shape sched groups per_wg".
+// Entries of the cache file written by this build:
+// "stamp|key shape sched groups per_wg csplit".
 void tune_cache_load(jacobi_ctx* c) {
     if (c->tune_loaded) return;
     c->tune_loaded = true;
@@ -342,8 +378,8 @@ void tune_cache_load(jacobi_ctx* c) {
         if (strcmp(line, kBuildStamp) != 0) continue;
         unsigned long long key = 0;
         BatchTune t;
-        if (sscanf(bar + 1, "%llu %d %d %d %d", &key, &t.shape, &t.sched, &t.groups,
-                   &t.per_wg) == 5)
+        if (sscanf(bar + 1, "%llu %d %d %d %d %d", &key, &t.shape, &t.sched, &t.groups,
+                   &t.per_wg, &t.csplit) == 6)
             c->batched_tune[(uint64_t)key] = t;
     }
     fclose(f);
@@ -356,8 +392,8 @@ void tune_cache_store(jacobi_ctx* c, uint64_t key, const BatchTune& t) {
     if (slash != std::string::npos) mkdir(c->tune_path.substr(0, slash).c_str(), 0755);
     FILE* f = fopen(c->tune_path.c_str(), "a");
     if (!f) return;
-    fprintf(f, "%s|%llu %d %d %d %d\n", kBuildStamp, (unsigned long long)key, t.shape, t.sched,
-            t.groups, t.per_wg);
+    fprintf(f, "%s|%llu %d %d %d %d %d\n", kBuildStamp, (unsigned long long)key, t.shape,
+            t.sched, t.groups, t.per_wg, t.csplit);
     fclose(f);
 }
 
@@ -370,7 +406,7 @@ int env_int(const char* name, int dflt) {
 
 jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, int32_t a_dtype,
                           const jacobi_options& o, int32_t test, double rel, hipStream_t s,
-                          jacobi_info* infos) {
+                          jacobi_info* infos, bool allow_split) {
     int kmax = 1;
     int64_t nmax = 1;
     double bytes = 0.0;
@@ -397,11 +433,29 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         f_shape = !strcmp(env, "wide") ? 0 : (!strcmp(env, "deep") ? 1 : -1);
     const int f_groups = env_int("JACOBI_BATCHED_GROUPS", -1);
     const int f_items = env_int("JACOBI_BATCHED_ITEMS", -1);
+    // Column split of a single system: chunks of at least 512 FP32 columns
+    // (1024 BF16, 256 FP64, i.e. 2 KiB of a row), so that the partial sums
+    // (2 x kt values per row and chunk) stay small next to A.
+    const int64_t minw = a_dtype == JACOBI_F64 ? 256 : (a_dtype == JACOBI_F32 ? 512 : 1024);
+    const bool splittable = allow_split && count == 1 && items[0].n >= 2 * minw;
+    int max_split = 1;
+    if (splittable)
+        while (max_split < 8 && items[0].n / (2 * max_split) >= minw) max_split *= 2;
+    const int f_split = splittable ? env_int("JACOBI_BATCHED_SPLIT", -1) : -1;
+    if (splittable) {
+        // rule: enough 64-row items times chunks to give every CU one
+        int cs = 1;
+        while (cs < max_split && (items[0].n + 63) / 64 * cs < c->num_cus) cs *= 2;
+        rule.csplit = cs;
+        rule.sched = 1;
+    }
     auto apply = [&](BatchTune t) {
         if (f_sched >= 0) t.sched = f_sched;
         if (f_shape >= 0) t.shape = f_shape;
         if (f_groups >= 1) t.groups = f_groups;
         if (f_items >= 1) t.per_wg = f_items;
+        if (f_split >= 1) t.csplit = std::min(f_split, max_split);
+        if (!splittable || t.sched != 1) t.csplit = 1;
         return t;
     };
     const char* tenv = getenv("JACOBI_TUNE");
@@ -414,7 +468,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         }
         return (uint64_t)b;
     };
-    const uint64_t key = ((uint64_t)(f_sched + 1) << 60) | ((uint64_t)a_dtype << 56) |
+    const uint64_t key = ((uint64_t)splittable << 62) | ((uint64_t)(f_sched + 1) << 60) |
+                         ((uint64_t)a_dtype << 56) |
                          ((uint64_t)(kmax <= 16 ? 16 : 32) << 48) | (lg(count) << 32) |
                          (lg((double)nmax) << 16) | lg(bytes);
     // Worth a search: at least about 32 MiB of sweeps expected (bytes of A
@@ -452,23 +507,47 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         HIP_TRY(hipStreamSynchronize(s));
     }
     const bool trace = getenv("JACOBI_BATCHED_TRACE") != nullptr;
-    BatchTune best{};
+    BatchTune best{}, last{};
     double best_ms = 1e300;
     auto trial = [&](BatchTune t) -> jacobi_status {
         t = apply(t);
         jacobi_status st = run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, t);
         if (st != JACOBI_OK) return st;
+        last = t;
         const double ms = infos[0].device_ms;
         if (trace)
-            std::fprintf(stderr, "jacobi tune: %s %s groups %d items %d: %.3f ms\n",
+            std::fprintf(stderr, "jacobi tune: %s %s groups %d items %d split %d: %.3f ms\n",
                          t.sched ? "lockstep" : "planned", t.shape ? "deep" : "wide", t.groups,
-                         t.per_wg, ms);
+                         t.per_wg, t.csplit, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = t;
         }
         return JACOBI_OK;
     };
+    if (splittable) {
+        // One system: the column split (lockstep) against the shapes.  The
+        // chunk count changes the summation order, so the chosen variant is
+        // run last: its output is the call's result, as on every later call.
+        for (int cs = 1; cs <= max_split; cs *= 2)
+            for (int sh : {0, 1}) {
+                if (f_shape >= 0 && sh != f_shape) continue;
+                if (f_split >= 1 && cs != std::min(f_split, max_split)) continue;
+                BatchTune t = rule;
+                t.shape = sh;
+                t.csplit = cs;
+                jacobi_status st = trial(t);
+                if (st != JACOBI_OK) return st;
+            }
+        if (!(best.shape == last.shape && best.csplit == last.csplit)) {
+            jacobi_status st =
+                run_batched_shape(c, count, items, a_dtype, o, test, rel, s, infos, best);
+            if (st != JACOBI_OK) return st;
+        }
+        c->batched_tune[key] = best;
+        tune_cache_store(c, key, best);
+        return JACOBI_OK;
+    }
     // stage 1: schedule x shape (the rule's candidate last, so that whatever
     // still favours a later run favours the default)
     std::vector<BatchTune> stage1;

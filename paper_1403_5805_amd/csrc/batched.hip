@@ -207,7 +207,8 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
 template <typename TA, int KT, int W, int TPW, int U>
 __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1,
                                            const float* xin, float* xout, float* red, int tid,
-                                           int wave, uint64_t& dmax, uint64_t& xmax, double& sq) {
+                                           int wave, uint64_t& dmax, uint64_t& xmax, double& sq,
+                                           int64_t c0, int64_t c1, float* part) {
     constexpr int LPL = 2;                     // 16-byte loads per lane and block
     constexpr int V16 = 16 / (int)sizeof(TA);  // A values per 16-byte load
     constexpr int VEC = LPL * V16;             // A values per lane and block
@@ -224,14 +225,19 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
     const int64_t n = S.n;
     const int64_t xld = S.xld;
     const int k = S.k;
-    const int64_t nb = (n + BW - 1) / BW;          // A blocks per row
+    // Columns [c0, c1) of the rows (the whole row unless the system's columns
+    // are split over workgroups; c0 is a multiple of W * BW, so block b
+    // stays with wave b % W).
+    const int64_t cn = c1 < n ? c1 : n;
+    const int64_t bst = c0 / BW;                   // first block
+    const int64_t nb = (cn + BW - 1) / BW;         // end of the blocks
     // Full blocks are read with 16-byte loads whatever the row alignment (a
     // row of n FP32 values starts 16-byte aligned only when n % 4 == 0): the
     // runtime runs kernels in unaligned access mode, where such a load costs
     // at most one more cache-line access and returns the same values.
-    const int64_t nbf = n / BW;
-    // this wave's vector-loadable blocks: b = wave + W * t, t < ntw
-    const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
+    const int64_t nbf = cn / BW;                   // end of the full blocks
+    // this wave's vector-loadable blocks: b = bst + wave + W * t, t < ntw
+    const int64_t ntw = nbf > bst + wave ? (nbf - bst - wave + W - 1) / W : 0;
     const int64_t nfull = (ntw / U) * U;
     gptr<float> xrow[NT];
 #pragma unroll
@@ -260,7 +266,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
                      f32x4 (&bx)[U][NT][NS], int64_t t0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t b = wave + W * (t0 + u);
+            const int64_t b = bst + wave + W * (t0 + u);
 #pragma unroll
             for (int q = 0; q < TPW; ++q)
 #pragma unroll
@@ -328,7 +334,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
                     for (int q = 0; q < TPW; ++q)
 #pragma unroll
                         for (int j = 0; j < LPL; ++j) unpack<TA>(v[u][q][j], a[q] + j * V16);
-                    mfma_block(a, bx[u], wave + W * (t0 + u));
+                    mfma_block(a, bx[u], bst + wave + W * (t0 + u));
                 }
             };
             // The scheduling barriers keep the compiler from sinking
@@ -364,7 +370,7 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
         preloaded = more && nfull > 0;
         if (preloaded) issue(arow_next, v0, b0, 0);
         // Remaining blocks of this wave (the ragged tail).
-        for (int64_t b = wave + W * nfull; b < nb; b += W) {
+        for (int64_t b = bst + wave + W * nfull; b < nb; b += W) {
             float a[TPW][VEC];
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
@@ -403,19 +409,21 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
         constexpr int EPT = TPW * NT * 256 / (W * 64);
         static_assert(EPT * W * 64 == TPW * NT * 256, "epilogue elements per thread");
         float e_xo[EPT], e_b[EPT], e_d[EPT];
+        if (!part) {
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int e = tid + u * W * 64;
-            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
-            const int q = qt / NT, t = qt - q * NT;
-            const int64_t i = pr + 16 * q + ri;
-            const int c = t * 16 + cc;
-            const bool ok = i < r1 && c < k;
-            const int64_t is = ok ? i : r0;  // a row and column that exist
-            const int cs = ok ? c : 0;
-            e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
-            e_b[u] = *gbl((const float*)S.bT + (int64_t)cs * xld + is);
-            e_d[u] = *gbl((const float*)S.diag + is);
+            for (int u = 0; u < EPT; ++u) {
+                const int e = tid + u * W * 64;
+                const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+                const int q = qt / NT, t = qt - q * NT;
+                const int64_t i = pr + 16 * q + ri;
+                const int c = t * 16 + cc;
+                const bool ok = i < r1 && c < k;
+                const int64_t is = ok ? i : r0;  // a row and column that exist
+                const int cs = ok ? c : 0;
+                e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
+                e_b[u] = *gbl((const float*)S.bT + (int64_t)cs * xld + is);
+                e_d[u] = *gbl((const float*)S.diag + is);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -429,7 +437,10 @@ __device__ __forceinline__ void sweep_rows(const BSys& S, int64_t r0, int64_t r1
             for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
             const int64_t i = pr + 16 * q + ri;
             const int c = t * 16 + cc;
-            if (i < r1 && c < k) {
+            if (part) {
+                // split columns: this chunk's partial sum, transposed
+                if (i < r1 && c < k) *gout(part + (int64_t)c * xld + i) = s;
+            } else if (i < r1 && c < k) {
                 const float xo = e_xo[u];
                 const float xn = (e_b[u] - s) / e_d[u];
                 *gout(xout + (int64_t)c * xld + i) = xn;
@@ -461,7 +472,8 @@ template <int KT, int W, int TPW, int U>
 __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_t r1,
                                                const double* xin, double* xout, double* red,
                                                int tid, int wave, uint64_t& dmax,
-                                               uint64_t& xmax, double& sq) {
+                                               uint64_t& xmax, double& sq, int64_t c0,
+                                               int64_t c1, double* part) {
     constexpr int BW = 16;       // columns of one A block
     constexpr int NT = KT / 16;  // 16-column output tiles
     const int lane = tid & 63, grp = lane >> 4, li = lane & 15;
@@ -469,9 +481,12 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
     const int64_t n = S.n;
     const int64_t xld = S.xld;
     const int k = S.k;
-    const int64_t nb = (n + BW - 1) / BW;  // A blocks per row
-    const int64_t nbf = n / BW;            // blocks entirely inside the row
-    const int64_t ntw = nbf > wave ? (nbf - wave + W - 1) / W : 0;
+    // columns [c0, c1), as in sweep_rows
+    const int64_t cn = c1 < n ? c1 : n;
+    const int64_t bst = c0 / BW;            // first block
+    const int64_t nb = (cn + BW - 1) / BW;  // end of the blocks
+    const int64_t nbf = cn / BW;            // end of the blocks entirely inside the row
+    const int64_t ntw = nbf > bst + wave ? (nbf - bst - wave + W - 1) / W : 0;
     const int64_t nfull = (ntw / U) * U;
     gptr<double> xrow[NT];
 #pragma unroll
@@ -494,7 +509,7 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
                      f64x2 (&bx)[U][NT][2], int64_t t0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t b = wave + W * (t0 + u);
+            const int64_t b = bst + wave + W * (t0 + u);
 #pragma unroll
             for (int q = 0; q < TPW; ++q)
 #pragma unroll
@@ -544,7 +559,7 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
             f64x2 b1[U][NT][2];
             auto consume = [&](f64x2 (&v)[U][TPW][2], f64x2 (&bx)[U][NT][2], int64_t t0) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) mfma_block(v[u], bx[u], wave + W * (t0 + u));
+                for (int u = 0; u < U; ++u) mfma_block(v[u], bx[u], bst + wave + W * (t0 + u));
             };
             if (!preloaded) issue(arow, v0, b0, 0);
             int64_t t = 0;
@@ -575,7 +590,7 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
         preloaded = more && nfull > 0;
         if (preloaded) issue(arow_next, v0, b0, 0);
         // Remaining blocks of this wave (the ragged tail).
-        for (int64_t b = wave + W * nfull; b < nb; b += W) {
+        for (int64_t b = bst + wave + W * nfull; b < nb; b += W) {
             f64x2 a[TPW][2];
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
@@ -607,19 +622,21 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
         constexpr int EPT = TPW * NT * 256 / (W * 64);
         static_assert(EPT * W * 64 == TPW * NT * 256, "epilogue elements per thread");
         double e_xo[EPT], e_b[EPT], e_d[EPT];
+        if (!part) {
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int e = tid + u * W * 64;
-            const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
-            const int q = qt / NT, t = qt - q * NT;
-            const int64_t i = pr + 16 * q + ri;
-            const int c = t * 16 + cc;
-            const bool ok = i < r1 && c < k;
-            const int64_t is = ok ? i : r0;
-            const int cs = ok ? c : 0;
-            e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
-            e_b[u] = *gbl((const double*)S.bT + (int64_t)cs * xld + is);
-            e_d[u] = *gbl((const double*)S.diag + is);
+            for (int u = 0; u < EPT; ++u) {
+                const int e = tid + u * W * 64;
+                const int ri = e & 15, cc = (e >> 4) & 15, qt = e >> 8;
+                const int q = qt / NT, t = qt - q * NT;
+                const int64_t i = pr + 16 * q + ri;
+                const int c = t * 16 + cc;
+                const bool ok = i < r1 && c < k;
+                const int64_t is = ok ? i : r0;
+                const int cs = ok ? c : 0;
+                e_xo[u] = *gbl(xin + (int64_t)cs * xld + is);
+                e_b[u] = *gbl((const double*)S.bT + (int64_t)cs * xld + is);
+                e_d[u] = *gbl((const double*)S.diag + is);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -633,7 +650,9 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
             for (int w = 0; w < W; ++w) s += red[(((w * TPW + q) * NT + t) * 4 + v) * 64 + l];
             const int64_t i = pr + 16 * q + ri;
             const int c = t * 16 + cc;
-            if (i < r1 && c < k) {
+            if (part) {
+                if (i < r1 && c < k) *gout(part + (int64_t)c * xld + i) = s;
+            } else if (i < r1 && c < k) {
                 const double xo = e_xo[u];
                 const double xn = (e_b[u] - s) / e_d[u];
                 *gout(xout + (int64_t)c * xld + i) = xn;
@@ -653,16 +672,21 @@ __device__ __forceinline__ void sweep_rows_f64(const BSys& S, int64_t r0, int64_
 }
 
 // The row sweep of a launch's element type.
+// Columns [c0, c1) only, with `part` non-null: the rows' partial sums over
+// those columns are written to `part` (transposed like the iterate) instead
+// of the epilogue.
 template <typename TA, int KT, int W, int TPW, int U>
 __device__ __forceinline__ void sweep_any(const BSys& S, int64_t r0, int64_t r1, const void* xin,
                                           void* xout, void* red, int tid, int wave,
-                                          uint64_t& dmax, uint64_t& xmax, double& sq) {
+                                          uint64_t& dmax, uint64_t& xmax, double& sq,
+                                          int64_t c0, int64_t c1, void* part) {
     if constexpr (std::is_same<TA, double>::value)
         sweep_rows_f64<KT, W, TPW, U>(S, r0, r1, (const double*)xin, (double*)xout,
-                                      (double*)red, tid, wave, dmax, xmax, sq);
+                                      (double*)red, tid, wave, dmax, xmax, sq, c0, c1,
+                                      (double*)part);
     else
         sweep_rows<TA, KT, W, TPW, U>(S, r0, r1, (const float*)xin, (float*)xout, (float*)red,
-                                      tid, wave, dmax, xmax, sq);
+                                      tid, wave, dmax, xmax, sq, c0, c1, (float*)part);
 }
 
 // ---------------------------------------------------------------------------
@@ -730,7 +754,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
             uint64_t dmax = 0, xmax = 0;
             double sq = 0.0;
             sweep_any<TA, KT, W, TPW, U>(S, job.r0, job.r1, xin, xout, red, tid, wave, dmax,
-                                         xmax, sq);
+                                         xmax, sq, 0, S.n, nullptr);
             // ---- workgroup reduction of the distance statistics
             dmax = wmax(dmax);
             xmax = wmax(xmax);
@@ -862,7 +886,9 @@ __global__ __launch_bounds__(W * 64, MINB) void k_batched(BatchArgs p) {
 // system swept (its copies done): every workgroup reads that round's count
 // after the barrier, and nothing changes the count after the barrier, so all
 // workgroups leave after the same round.
-template <typename TA, int KT, int W, int TPW, int U, int MINB>
+//   SPLIT  compiled with the column split (one system per launch); the
+//          batched launches run the variant without it
+template <typename TA, int KT, int W, int TPW, int U, int MINB, bool SPLIT>
 __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     using TX = typename IterOf<TA>::T;
     constexpr int NT = KT / 16;
@@ -980,10 +1006,12 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                 continue;
             }
             if (act == ACT_COPY || act == ACT_STOP) {
-                // stopped after sweep r - 1: this item's rows of the final iterate
+                // stopped after sweep r - 1: this item's rows of the final
+                // iterate (one chunk of a split row range copies them)
                 const TX* xsrc = (const TX*)(((r - 1) & 1) ? S.buf1 : S.buf0);
                 const int k = S.k;
-                for (int64_t e = tid; e < (int64_t)(item.r1 - item.r0) * k; e += W * 64) {
+                const int64_t ncopy = (SPLIT && item.rank != 0) ? 0 : item.r1 - item.r0;
+                for (int64_t e = tid; e < ncopy * k; e += W * 64) {
                     const int64_t i = item.r0 + e / k;
                     const int c = (int)(e % k);
                     ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
@@ -1014,8 +1042,62 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
             double sq = 0.0;
             const TX* xin = (const TX*)((r & 1) ? S.buf0 : S.buf1);
             TX* xout = (TX*)((r & 1) ? S.buf1 : S.buf0);
-            sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave, dmax,
-                                         xmax, sq);
+            int32_t qslot = it;  // where this item's sum of squares goes
+            if constexpr (!SPLIT) {
+                sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
+                                             dmax, xmax, sq, 0, S.n, nullptr);
+            } else {
+                // Column chunk item.rank of rows [r0, r1): partial sums only.
+                const int32_t cs = S.csplit;
+                const int32_t rr0 = S.it0 + (it - S.it0) / cs * cs;  // the range's first item
+                const int64_t c0 = (int64_t)item.rank * S.cw;
+                const int64_t c1 = c0 + S.cw < S.n ? c0 + S.cw : S.n;
+                TX* part = (TX*)S.part;
+                sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave,
+                                             dmax, xmax, sq, c0, c1,
+                                             part + (size_t)item.rank * KT * S.xld);
+                // every partial-sum store precedes thread 0's release (the
+                // row sweep ends with a workgroup barrier)
+                if (tid == 0) {
+                    const uint32_t t = __hip_atomic_fetch_add(&p.rcnt[rr0], 1u, __ATOMIC_RELEASE,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                    const bool lastc = t + 1 == (uint32_t)cs;
+                    if (lastc) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        __hip_atomic_store(&p.rcnt[rr0], 0u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    s_act = lastc ? 1 : 0;
+                }
+                __syncthreads();
+                if (s_act) {
+                    // the last chunk: chunk sums in chunk order, then the epilogue
+                    const int64_t rows = item.r1 - item.r0;
+                    const int k = S.k;
+                    const int64_t xld = S.xld;
+                    for (int64_t e = tid; e < rows * k; e += W * 64) {
+                        const int c = (int)(e / rows);
+                        const int64_t i = item.r0 + e % rows;
+                        TX acc = TX(0);
+                        for (int32_t ch = 0; ch < cs; ++ch)
+                            acc += part[(size_t)ch * KT * xld + (int64_t)c * xld + i];
+                        const TX xo = xin[(int64_t)c * xld + i];
+                        const TX xn = (((const TX*)S.bT)[(int64_t)c * xld + i] - acc) /
+                                      ((const TX*)S.diag)[i];
+                        xout[(int64_t)c * xld + i] = xn;
+                        const double dd = fabs((double)xn - (double)xo);
+                        const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                        dmax = db > dmax ? db : dmax;
+                        xmax = mb > xmax ? mb : xmax;
+                        sq += dd * dd;
+                    }
+                }
+                qslot = s_act ? rr0 : -1;
+                if (s_act && tid == 0)
+                    for (int32_t j = 1; j < cs; ++j)  // the range's other slots hold zero
+                        __hip_atomic_store(&p.item_parts[(size_t)par * p.nitems + rr0 + j], 0.0,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             dmax = wmax(dmax);
             xmax = wmax(xmax);
             sq = wsum(sq);
@@ -1034,8 +1116,8 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                     Q += red_s[w];
                 }
                 const int slot = r % 3;
-                if (S.norm == 1)
-                    __hip_atomic_store(&p.item_parts[(size_t)par * p.nitems + it], Q,
+                if (S.norm == 1 && qslot >= 0)
+                    __hip_atomic_store(&p.item_parts[(size_t)par * p.nitems + qslot], Q,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_max(&st->dmax[slot], D, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1145,24 +1227,34 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
     return hipGetLastError();
 }
 
-template <typename TA, int KT>
+template <typename TA, int KT, bool SPLIT>
 static const void* rounds_fn(int variant) {
-    if (variant == 1) return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 1), kBU, 1>;
-    return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2>;
+    if (variant == 1)
+        return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 1), kBU, 1, SPLIT>;
+    return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2, SPLIT>;
 }
 
-static const void* pick_rounds(int32_t a_dtype, int32_t kt, int variant) {
+template <bool SPLIT>
+static const void* pick_rounds_t(int32_t a_dtype, int32_t kt, int variant) {
     if (a_dtype == 0)
-        return kt <= 16 ? rounds_fn<double, 16>(variant) : rounds_fn<double, 32>(variant);
+        return kt <= 16 ? rounds_fn<double, 16, SPLIT>(variant)
+                        : rounds_fn<double, 32, SPLIT>(variant);
     if (a_dtype == 1)
-        return kt <= 16 ? rounds_fn<float, 16>(variant) : rounds_fn<float, 32>(variant);
+        return kt <= 16 ? rounds_fn<float, 16, SPLIT>(variant)
+                        : rounds_fn<float, 32, SPLIT>(variant);
     if (a_dtype == 2)
-        return kt <= 16 ? rounds_fn<bf16_t, 16>(variant) : rounds_fn<bf16_t, 32>(variant);
+        return kt <= 16 ? rounds_fn<bf16_t, 16, SPLIT>(variant)
+                        : rounds_fn<bf16_t, 32, SPLIT>(variant);
     return nullptr;
 }
 
-int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus) {
-    const void* fn = pick_rounds(a_dtype, kt, variant);
+static const void* pick_rounds(int32_t a_dtype, int32_t kt, int variant, bool split) {
+    return split ? pick_rounds_t<true>(a_dtype, kt, variant)
+                 : pick_rounds_t<false>(a_dtype, kt, variant);
+}
+
+int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus, bool split) {
+    const void* fn = pick_rounds(a_dtype, kt, variant, split);
     if (!fn) return 0;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, 0) != hipSuccess ||
@@ -1172,8 +1264,8 @@ int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus) {
 }
 
 hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
-                         hipStream_t s) {
-    const void* fn = pick_rounds(a_dtype, kt, variant);
+                         hipStream_t s, bool split) {
+    const void* fn = pick_rounds(a_dtype, kt, variant, split);
     if (!fn) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* args[] = {&copy};

@@ -27,6 +27,7 @@ struct BatchTune {
     int sched = 1;   // 0 planned, 1 lockstep
     int groups = 1;  // lockstep: XCD groups of work items (1 = none)
     int per_wg = 8;  // lockstep: work items per workgroup and round
+    int csplit = 1;  // lockstep, one system: column chunks (split-K); 1 = none
 };
 
 // Grow-only pinned, device-mapped host buffer for the small per-call

@@ -151,6 +151,16 @@ struct BSys {
     double rel;        // TEST_REL factor
     int32_t norm;      // 0 inf, 1 l2
     int32_t it0, it1;  // lockstep schedule: the system's work items [it0, it1)
+    // Column split (lockstep schedule, one system per launch): the columns
+    // are cut into csplit chunks of cw columns (a multiple of the workgroup's
+    // block span); item it0 + r * csplit + c covers chunk c of row range r and
+    // writes its partial sums to part + c * kt * xld (transposed); the last
+    // chunk of a row range to finish adds them in chunk order.  csplit = 1:
+    // no split.
+    int32_t csplit;
+    int32_t pad;
+    int64_t cw;
+    void* part;
 };
 
 // Per-system control state (device), zeroed before the launch.
@@ -207,6 +217,8 @@ struct BatchArgs {
     double* item_parts;       // [2][nitems] L2 partial sums of the sweep, by round parity
     BCtl* ctl;
     const int32_t* group_off; // [ngroups + 1]: items of group q are [group_off[q], group_off[q+1])
+    uint32_t* rcnt;           // [nitems]: chunks of a row range done this round (split systems,
+                              // at the range's first item), zero between rounds
     int32_t ngroups;          // 0 (no items) .. kMaxGroups
     int32_t nitems;
     int32_t active0;          // systems with max_iter > 0
@@ -219,9 +231,10 @@ hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchA
                           hipStream_t s);
 // The lockstep schedule: every workgroup sweeps work items of any system, all
 // systems advance one sweep per round, one grid barrier per round.
+// split: the kernel compiled with the column split of a single system.
 hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
-                         hipStream_t s);
-int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
+                         hipStream_t s, bool split = false);
+int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus, bool split = false);
 int batched_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 
 // ---------------------------------------------------------------------------

@@ -208,7 +208,8 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
             io.tol = 0.0;
             io.max_iter = o.max_inner;
             jacobi_info ii{};
-            jacobi_status st = run_batched(c, 1, &it, lo, io, TEST_REL, o.inner_rel_tol, s, &ii);
+            jacobi_status st =
+                run_batched(c, 1, &it, lo, io, TEST_REL, o.inner_rel_tol, s, &ii, true);
             if (st != JACOBI_OK) return st;
             if (ii.status < 0) return (jacobi_status)ii.status;
             inner_total += ii.iterations;

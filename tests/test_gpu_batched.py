@@ -458,3 +458,66 @@ def test_many_small_systems_stop_in_different_rounds(jac, dtype):
     assert all(z["iterations"] == 0 and z["status"] == jac.NOT_CONVERGED for z in zinfo)
     counts = {int(i["iterations"]) for i in infos if i["status"] == jac.OK}
     assert len(counts) >= 3, counts
+
+
+@pytest.mark.parametrize("dtype,n,k,pad", [("f32", 4096, 16, 0), ("f32", 3001, 5, 1),
+                                           ("bf16", 4096, 8, 0), ("f64", 2048, 4, 0),
+                                           ("f64", 1999, 32, 1)])
+def test_column_split_parity(jac, monkeypatch, dtype, n, k, pad):
+    """A single system with its columns split over workgroups (split-K: each
+    chunk's partial sums, added in chunk order by the range's last chunk):
+    every chunk count agrees with the oracle (FP32/BF16 at 1e-5, FP64 at
+    1e-12 with the oracle's count), ragged last chunks and rows that are not
+    16-byte aligned included; each split is deterministic (bitwise on
+    repeat); the Euclidean norm with a fixed sweep count agrees too."""
+    import torch
+    if dtype == "f64":
+        A, _, B = synth.dominant(n, k, 3100 + n + k, synth.ADDITIVE, 1.0, 2.0)
+        Ap, Bp, tol, bar = A, B, 1e-11, REL_F64
+        tdt, vdt = torch.float64, torch.float64
+    else:
+        A32, _, B32 = _sys32(n, k, 3100 + n + k)
+        Ap = (torch.from_numpy(A32).to(torch.bfloat16).to(torch.float64).numpy()
+              if dtype == "bf16" else A32.astype(np.float64))
+        A, B, Bp, tol, bar = A32, B32, B32.astype(np.float64), 1e-6, REL_F32
+        tdt, vdt = (torch.bfloat16 if dtype == "bf16" else torch.float32), torch.float32
+    big = torch.zeros((n, n + pad), dtype=torch.float64)
+    big[:, :n] = torch.from_numpy(np.asarray(A, dtype=np.float64))
+    Ad = big.to(tdt).cuda()[:, :n]
+    Bd = torch.from_numpy(B).to(vdt).cuda()
+    xo, io = oracle.jacobi(Ap, Bp, tol=tol, max_iter=500)
+    xl2, _ = oracle.jacobi(Ap, Bp, tol=0.0, max_iter=5, norm="l2")
+    margin = tie_margin(Ap, Bp, tol, io["iterations"]) if dtype == "f64" else 0.0
+    for cs in (1, 2, 4, 8):
+        monkeypatch.setenv("JACOBI_BATCHED_SPLIT", str(cs))
+        say("column split", dtype, n, k, pad, cs)
+        X, info = jac.solve(Ad, Bd, tol=tol, max_iter=500)
+        assert info["status"] == jac.OK, (cs, info)
+        if dtype == "f64" and margin > 1e-6:
+            assert info["iterations"] == io["iterations"], (cs, info, io)
+        else:
+            assert abs(info["iterations"] - io["iterations"]) <= 1, (cs, info, io)
+        assert rel_err(host(X), xo) <= bar, cs
+        X2, info2 = jac.solve(Ad, Bd, tol=tol, max_iter=500)
+        assert torch.equal(X, X2) and info2["iterations"] == info["iterations"]
+        X3, info3 = jac.solve(Ad, Bd, tol=0.0, max_iter=5, norm="l2")
+        assert info3["iterations"] == 5 and rel_err(host(X3), xl2) <= bar, cs
+    monkeypatch.delenv("JACOBI_BATCHED_SPLIT")
+
+
+def test_column_split_tuned_deterministic(jac, monkeypatch):
+    """Untuned class: the first solve tries every chunk count and shape and
+    returns the chosen variant's result, so the first and later solves of the
+    class agree bitwise; the chosen variant is reported in info['kernel']."""
+    import torch
+    A32, _, B32 = _sys32(6000, 12, 3300)
+    Ad, Bd = dev(A32), dev(B32)
+    monkeypatch.setenv("JACOBI_TUNE", "always")
+    say("column split tuned")
+    X1, i1 = jac.solve(Ad, Bd, tol=1e-6, max_iter=300)
+    monkeypatch.setenv("JACOBI_TUNE", "auto")
+    X2, i2 = jac.solve(Ad, Bd, tol=1e-6, max_iter=300)
+    assert torch.equal(X1, X2) and i1["iterations"] == i2["iterations"]
+    assert i1["kernel"] == i2["kernel"] and (i1["kernel"] & 1)
+    xo, io = _oracle32(A32, B32, 1e-6, 300)
+    assert rel_err(host(X1), xo) <= REL_F32
