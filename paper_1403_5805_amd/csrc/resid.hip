@@ -143,11 +143,14 @@ __global__ __launch_bounds__(W * 64) void k_resid(RArgs p) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 const double* src = arow[q] + b * BW;
+                // ordinary loads: each 128-byte line of a row is shared by
+                // the blocks of two waves, and non-temporal loads could fetch
+                // it twice
                 if constexpr (VEC16) {
-                    a[q] = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
+                    a[q] = *reinterpret_cast<const f64x2*>(src);
                 } else {
-                    a[q].x = __builtin_nontemporal_load(src);
-                    a[q].y = __builtin_nontemporal_load(src + 1);
+                    a[q].x = src[0];
+                    a[q].y = src[1];
                 }
             }
         };
