@@ -55,22 +55,28 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# HBM bytes per sweep launch at n = 16384 from the FETCH_SIZE / WRITE_SIZE
-# counter runs (scaled by a 1 GiB reference copy), valid for the sweep source
-# with this sha256 prefix only.
-SWEEP_TRAFFIC = {"sha256_prefix": "c8315b341a0ac5d7", "n": 16384, "bytes": 1074596646}
+# Fabric bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs
+# (each scaled by what the counter reads for a 1 GiB reference copy), valid
+# only for the kernel source with this sha256 prefix (profiles/ has the runs):
+# the FP32 sweep at n = 16384, and the batched launch of the 256-system
+# workload (deep shape, 16 items per workgroup).
+SWEEP_TRAFFIC = {"src": "sweep.hip", "sha256_prefix": "2a8f2d8cacc75a29", "n": 16384,
+                 "bytes": 1074620084}
+C3_TRAFFIC = {"src": "batched.hip", "sha256_prefix": "5cf67cfd9905f68f", "bytes": 21110416755}
 
 
-def _sweep_traffic(n: int):
+def _traffic(rec):
     import hashlib
-    src = os.path.join(ROOT, "paper_1403_5805_amd", "csrc", "sweep.hip")
+    src = os.path.join(ROOT, "paper_1403_5805_amd", "csrc", rec["src"])
     try:
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if h != SWEEP_TRAFFIC["sha256_prefix"] or n != SWEEP_TRAFFIC["n"]:
-        return None
-    return SWEEP_TRAFFIC["bytes"]
+    return rec["bytes"] if h == rec["sha256_prefix"] else None
+
+
+def _sweep_traffic(n: int):
+    return _traffic(SWEEP_TRAFFIC) if n == SWEEP_TRAFFIC["n"] else None
 
 
 def sweep_bytes_f32(n: int, k: int = 1) -> int:
@@ -432,9 +438,12 @@ def bench_c3(args):
     res["all_ok"] = ok
     res["step_ms"] = step_ms
     res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
+    code = infos[0]["kernel"]
+    measured = code == (1 | 2 | (16 << 8) | (1 << 16))  # the variant the counters measured
     res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                       "kernel": _batched_kernel_name(infos[0]["kernel"], "float", 32),
+                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "traffic": _traffic(C3_TRAFFIC) if measured else None,
+                       "kernel": _batched_kernel_name(code, "float", 32),
                        "mfma_tflops": round(tfs, 2),
                        "mfma_frac_of_157_3": round(tfs / 157.3, 4),
                        "launch_device_ms": round(dev_ms, 3)}
