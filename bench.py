@@ -360,15 +360,23 @@ def bench_c1(args):
 
 def _batched_kernel_name(code: int, ta: str, kt: int) -> str:
     """Kernel that ran a batched solve, from jacobi_info.kernel (bit 0:
-    lockstep schedule, bit 1: deep shape, bits 2-4: XCD groups - 1, bits 8-15:
-    items per workgroup, bits 16+: column chunks) and its template shape."""
+    lockstep schedule, bit 6: dataflow schedule, bit 1: deep shape, bits 2-4:
+    XCD groups - 1, bits 8-15: items per workgroup, bits 16+: column chunks)
+    and its template shape."""
     deep = bool(code & 2)
-    tpw = 4 if (deep or (kt <= 16 and ta == "float")) else 2
-    name = "k_rounds" if code & 1 else "k_batched"
+    flow = bool(code & 64)
+    whole = bool(code & 65) and (code >> 16) <= 1
+    if deep:
+        tpw = 8 if whole and (ta == "float" or (ta == "bf16" and kt <= 16)) else 4
+    else:
+        tpw = 4 if (kt <= 16 and ta == "float") else 2
+    name = "k_rounds" if code & 1 else ("k_flow" if flow else "k_batched")
+    sched = "lockstep" if code & 1 else ("dataflow" if flow else "planned")
     extra = (f"; {((code >> 2) & 7) + 1} XCD group(s), {(code >> 8) & 0xff} items per "
-             f"workgroup, {max(1, code >> 16)} column chunk(s)" if code & 1 else "")
+             f"workgroup, {max(1, code >> 16)} column chunk(s)" if code & 1 else
+             (f"; {(code >> 8) & 0xff} items per workgroup" if flow else ""))
     return (f"{name}<{ta},KT={kt},W=4,TPW={tpw},U=1> ({'deep, 1' if deep else 'wide, 2'} "
-            f"workgroup(s) per CU; {'lockstep' if code & 1 else 'planned'} schedule{extra})")
+            f"workgroup(s) per CU; {sched} schedule{extra})")
 
 
 def bench_c3(args):

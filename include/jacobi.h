@@ -104,11 +104,12 @@ typedef struct {
     int32_t status;           /* jacobi_status of this system                            */
     int32_t iterations;       /* sweeps executed (REFINE: inner sweeps, all corrections)  */
     int32_t outer_iterations; /* REFINE: residual evaluations; PLAIN: 0                  */
-    int32_t kernel;           /* batched-kernel solves: bit 0 lockstep schedule (else
-                                 planned), bit 1 deep shape (one workgroup per CU, else two),
-                                 bits 2-4 XCD groups - 1, bits 8-15 work items per
-                                 workgroup (lockstep), bits 16+ column chunks of a split
-                                 single system (1 = none); 0 for other solves               */
+    int32_t kernel;           /* batched-kernel solves: bit 0 lockstep schedule, bit 6
+                                 dataflow schedule (neither: planned), bit 1 deep shape
+                                 (one workgroup per CU, else two), bits 2-4 XCD groups - 1
+                                 (lockstep), bits 8-15 work items per workgroup (lockstep,
+                                 dataflow), bits 16+ column chunks of a split single system
+                                 (1 = none); 0 for other solves                             */
     int64_t bad_index;        /* first offending row for ZERO_DIAGONAL / NONFINITE, or -1 */
     double final_delta;       /* distance of the last executed sweep (-1 if none)        */
     double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */
@@ -172,14 +173,17 @@ typedef struct {
  * persistent launch.  a_dtype F64: A, B, X0, X double, FP64 MFMA tiles
  * (v_mfma_f64_16x16x4f64, FP64 accumulation); F32 or BF16: A as given,
  * B/X0/X float, FP32 MFMA tiles with FP32 accumulation.  Every system has
- * k <= 32 (others get JACOBI_ERR_INVALID_ARG).  The sweeps run in rounds: round r is sweep r
- * of every system still running, its rows dealt out to all workgroups as work
- * items, one device-wide barrier per round (the earlier schedule, with split
- * systems meeting at per-system barriers and small systems taken whole from a
- * queue, is selected by the environment variable JACOBI_BATCHED_SCHED=planned;
- * both give bitwise the same X).  Every system stops on its own (opt->tol /
- * opt->max_iter, PLAIN mode only, INF or L2 distance over its n*k entries) and
- * leaves the rounds.
+ * k <= 32 (others get JACOBI_ERR_INVALID_ARG).  Three schedules run the same
+ * row sweep and give bitwise the same X: lockstep (round r is sweep r of every
+ * system still running, its rows dealt out to all workgroups as work items,
+ * one device-wide barrier per round), dataflow (no rounds: a system's next
+ * sweep is queued as work items the moment the last item of its current
+ * sweep finishes) and planned (large systems split over workgroups that meet
+ * at per-system barriers, small ones taken whole from a queue).  The first
+ * batch of a kind is timed on the candidates and the fastest is kept (in the
+ * context and a per-user cache file); JACOBI_BATCHED_SCHED = lockstep |
+ * dataflow | planned forces one.  Every system stops on its own (opt->tol /
+ * opt->max_iter, PLAIN mode only, INF or L2 distance over its n*k entries).
  *
  * systems, infos: host arrays of `count` entries.  Returns JACOBI_OK when the
  * launch ran (per-system outcomes in infos[i].status; a system with bad

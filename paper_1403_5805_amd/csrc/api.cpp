@@ -103,7 +103,7 @@ void ctx_release(jacobi_ctx* c) {
     hipSetDevice(c->device);
     for (DevBuf* b : {&c->diag, &c->w0, &c->w1, &c->alo, &c->diag_lo, &c->xa, &c->xb, &c->r64,
                       &c->rlo, &c->d0, &c->d1, &c->scal, &c->bws, &c->bmeta, &c->rmeta,
-                      &c->xT, &c->warm})
+                      &c->xT, &c->warm, &c->fring})
         b->release();
     c->stage.release();
     if (c->bev_begin) hipEventDestroy(c->bev_begin);

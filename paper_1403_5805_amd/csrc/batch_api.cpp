@@ -84,24 +84,35 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
                                        int32_t a_dtype, const jacobi_options& o, int32_t test,
                                        double rel, hipStream_t s, jacobi_info* infos,
                                        const BatchTune& tune) {
-    const int variant = tune.shape, sched = tune.sched;
+    const int variant = tune.shape;
+    int sched = tune.sched;
     int kmax = 1;
     int64_t nmax = 1;
+    double rows_iter = 0.0;  // bounds the dataflow queue (items x max_iter)
     for (int i = 0; i < count; ++i) {
         kmax = std::max<int>(kmax, (int)items[i].k);
         nmax = std::max(nmax, items[i].n);
+        rows_iter += (double)items[i].n * (double)std::max(0, (int)items[i].max_iter);
     }
+    // The dataflow queue holds every item a launch may publish: the items of
+    // each system times its max_iter, at most 32 Mi entries (256 MiB); a
+    // batch that could need more (a huge sweep cap) runs the lockstep
+    // schedule.  Every item has at least 16 rows, so rows / 16 bounds the
+    // item count before the plan is made.
+    if (sched == 2 && (rows_iter / 16.0 > (double)(1ull << 25) || (count == 1 && tune.csplit > 1)))
+        sched = 1;
     const int kt = kmax <= 16 ? 16 : 32;
     const bool split = sched == 1 && count == 1 && tune.csplit > 1;
-    const int capacity = sched == 1 ? rounds_max_grid(a_dtype, kt, variant, c->num_cus, split)
-                                    : batched_max_grid(a_dtype, kt, variant, c->num_cus);
+    const int capacity = sched == 2   ? flow_max_grid(a_dtype, kt, variant, c->num_cus)
+                         : sched == 1 ? rounds_max_grid(a_dtype, kt, variant, c->num_cus, split)
+                                      : batched_max_grid(a_dtype, kt, variant, c->num_cus);
     if (capacity < 1) {
         set_error("batched kernel unavailable for this dtype");
         return JACOBI_ERR_INVALID_ARG;
     }
     std::vector<int64_t> ns(count);
     for (int i = 0; i < count; ++i) ns[i] = items[i].n;
-    const int tpp = batched_tiles_per_pass(a_dtype, kt, variant);
+    const int tpp = batched_tiles_per_pass(a_dtype, kt, variant, sched >= 1 && !split);
     Plan plan;
     ItemPlan ip;
     int grid = 0;
@@ -129,8 +140,9 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         ip.g_off = {0, (int32_t)ip.items.size()};
         ip.grid = std::min<int>(capacity, (int)ip.items.size());
         grid = ip.grid;
-    } else if (sched == 1) {
-        ip = make_items(ns, capacity, tpp, (int)ea, std::min(kMaxGroups, std::max(1, tune.groups)),
+    } else if (sched >= 1) {
+        ip = make_items(ns, capacity, tpp, (int)ea,
+                        sched == 2 ? 1 : std::min(kMaxGroups, std::max(1, tune.groups)),
                         tune.per_wg);
         grid = ip.grid;
     } else {
@@ -160,9 +172,10 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     // device metadata: [sys | st | schedule tables (uploaded) | partial sums]
     //   sched 0 tables: jobs | job_off | queue head (16 bytes) + queue
     //   sched 1 tables: items | group offsets | BCtl
+    //   sched 2 tables: items | group offsets | BCtl
     const size_t sys_b = align(sizeof(BSys) * count), st_b = align(sizeof(BState) * count);
     size_t job_b = 0, off_b = 0, q_b = 0, parts_b = 0;
-    if (sched == 1) {
+    if (sched >= 1) {
         job_b = align(sizeof(BJob) * std::max<size_t>(1, ip.items.size()));
         // group offsets, then the row-range counters of a split system
         off_b = align(sizeof(int32_t) * ip.g_off.size() +
@@ -209,7 +222,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         S.n = it.n;
         S.k = (int32_t)it.k;
         S.csplit = 1;
-        if (sched == 1) {
+        if (sched >= 1) {
             S.nwg = 1;
             S.it0 = ip.it0[i];
             S.it1 = ip.it1[i];
@@ -246,13 +259,42 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     std::memcpy(h, hs.data(), sizeof(BSys) * count);
     std::memcpy(h + sys_b, hst.data(), sizeof(BState) * count);
     char* ht = h + sys_b + st_b;
-    if (sched == 1) {
+    // Dataflow schedule: queue positions [0, nitems) are the items of every
+    // system's first work (sweep 1, or the copy-out of X0 when max_iter = 0);
+    // the ring holds every item a launch can publish later: the items of
+    // sweeps 2 .. max_iter and of the copy-out, max_iter works per system.
+    uint64_t ring_cap = 0;
+    if (sched == 2) {
+        for (int i = 0; i < count; ++i) {
+            BState& T = hst[i];
+            T.work = items[i].max_iter > 0 ? 2 : 1;
+            ring_cap += (uint64_t)(ip.it1[i] - ip.it0[i]) *
+                        (uint64_t)std::max(0, (int)items[i].max_iter);
+        }
+        ring_cap = std::max<uint64_t>(ring_cap, 1);
+        std::memcpy(h + sys_b, hst.data(), sizeof(BState) * count);
+        const size_t ring_b = sizeof(uint64_t) * ring_cap;
+        if (c->fring.bytes < ring_b) {
+            HIP_TRY(c->fring.ensure(ring_b));
+            HIP_TRY(hipMemsetAsync(c->fring.p, 0, c->fring.bytes, s));  // no stale tags
+            c->flow_gen = 0;
+        }
+        if (++c->flow_gen == 0) {  // tags wrapped: clear them
+            HIP_TRY(hipMemsetAsync(c->fring.p, 0, c->fring.bytes, s));
+            c->flow_gen = 1;
+        }
+    }
+    if (sched >= 1) {
         std::memcpy(ht, ip.items.data(), sizeof(BJob) * ip.items.size());
         std::memset(ht + job_b, 0, off_b);
         std::memcpy(ht + job_b, ip.g_off.data(), sizeof(int32_t) * ip.g_off.size());
         BCtl ctl;
         std::memset(&ctl, 0, sizeof(ctl));
-        ctl.active = (uint32_t)active0;
+        // dataflow: every system with items is active until its copy-out
+        int32_t with_items = 0;
+        for (int i = 0; i < count; ++i) with_items += ip.it1[i] > ip.it0[i] ? 1 : 0;
+        ctl.active = (uint32_t)(sched == 2 ? with_items : active0);
+        ctl.ftail = (uint32_t)ip.items.size();
         std::memcpy(ht + job_b + off_b, &ctl, sizeof(ctl));
     } else {
         if (!plan.jobs.empty()) std::memcpy(ht, plan.jobs.data(), sizeof(BJob) * plan.jobs.size());
@@ -275,7 +317,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         rate_khz <= 0)
         rate_khz = 100000;
     ba.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
-    if (sched == 1) {
+    if (sched >= 1) {
         ba.items = d_jobs;
         ba.item_parts = d_parts;
         ba.ctl = (BCtl*)d_q;
@@ -285,7 +327,14 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         ba.nitems = (int32_t)ip.items.size();
         ba.active0 = active0;
         ba.max_rounds = max_rounds;
-        if (grid > 0) HIP_TRY(launch_rounds(a_dtype, kt, variant, ba, grid, s, csplit > 1));
+        if (sched == 2) {
+            ba.ring = (uint64_t*)c->fring.p;
+            ba.ring_cap = (uint32_t)ring_cap;
+            ba.gen = c->flow_gen;
+            if (grid > 0) HIP_TRY(launch_flow(a_dtype, kt, variant, ba, grid, s));
+        } else if (grid > 0) {
+            HIP_TRY(launch_rounds(a_dtype, kt, variant, ba, grid, s, csplit > 1));
+        }
     } else {
         ba.jobs = d_jobs;
         ba.job_off = d_off;
@@ -298,29 +347,30 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     }
     HIP_TRY(hipEventRecord(c->bev_end, s));
     HIP_TRY(launch_copy16(d_st, (char*)c->stage.d + up_b, st_b, s));
-    if (sched == 1) HIP_TRY(launch_copy16(d_q, (char*)c->stage.d + up_b + st_b, q_b, s));
+    if (sched >= 1)
+        HIP_TRY(launch_copy16(d_q, (char*)c->stage.d + up_b + st_b, align(sizeof(BCtl)), s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(hst.data(), h + up_b, sizeof(BState) * count);
-    if (sched == 1) {
+    if (sched >= 1) {
         BCtl ctl;
         std::memcpy(&ctl, h + up_b + st_b, sizeof(ctl));
-        if (ctl.abort)  // a grid barrier timed out: no outcome is trustworthy
+        if (ctl.abort)  // a wait timed out: no outcome is trustworthy
             for (int i = 0; i < count; ++i) hst[i].error = 1;
     }
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
     decode_states(hst.data(), count, ms,
-                  (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0) |
+                  (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0) | (sched == 2 ? 64 : 0) |
                       (sched == 1 ? (std::min(tune.groups, kMaxGroups) - 1) << 2 : 0) |
-                      (sched == 1 ? tune.per_wg << 8 : 0) | (csplit << 16),
+                      (sched >= 1 ? tune.per_wg << 8 : 0) | (csplit << 16),
                   infos);
     return JACOBI_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Tuning.  Every variant of a batched launch -- schedule (lockstep or planned),
-// kernel shape (wide or deep), XCD grouping and items per workgroup of the
-// lockstep schedule -- sums every element in the same order, so all of them
+// Tuning.  Every variant of a batched launch -- schedule (planned, lockstep
+// or dataflow), kernel shape (wide or deep), XCD grouping and items per
+// workgroup of the lockstep schedule -- sums every element in the same order, so all of them
 // give bitwise the same X, counts and maximum-norm distances (tested); only
 // the time differs.  The first batch of a class (schedule choice, element
 // type, output width, and the power-of-two classes of system count, largest
@@ -329,8 +379,9 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
 // is kept: in the context for its life, and in a cache file (one per GPU
 // architecture, HIP runtime and library build) that later processes read.
 // The search is staged: schedule x shape first, then for the lockstep
-// schedule the XCD grouping and the items per workgroup, one at a time.
-// Environment overrides: JACOBI_BATCHED_SCHED (lockstep | planned),
+// schedule the XCD grouping, and for the lockstep and dataflow schedules the
+// items per workgroup, one at a time.
+// Environment overrides: JACOBI_BATCHED_SCHED (planned | lockstep | dataflow),
 // JACOBI_BATCHED_SHAPE (wide | deep), JACOBI_BATCHED_GROUPS (1..8),
 // JACOBI_BATCHED_ITEMS (items per workgroup), JACOBI_TUNE (auto | off |
 // always), JACOBI_TUNE_CACHE (file path, or "off").
@@ -428,7 +479,10 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     // Overrides fix a parameter and keep it out of the search.
     int f_sched = -1, f_shape = -1;
     if (const char* env = getenv("JACOBI_BATCHED_SCHED"))
-        f_sched = !strcmp(env, "planned") ? 0 : (!strcmp(env, "lockstep") ? 1 : -1);
+        f_sched = !strcmp(env, "planned")    ? 0
+                  : !strcmp(env, "lockstep") ? 1
+                  : !strcmp(env, "dataflow") ? 2
+                                             : -1;
     if (const char* env = getenv("JACOBI_BATCHED_SHAPE"))
         f_shape = !strcmp(env, "wide") ? 0 : (!strcmp(env, "deep") ? 1 : -1);
     const int f_groups = env_int("JACOBI_BATCHED_GROUPS", -1);
@@ -517,8 +571,8 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         const double ms = infos[0].device_ms;
         if (trace)
             std::fprintf(stderr, "jacobi tune: %s %s groups %d items %d split %d: %.3f ms\n",
-                         t.sched ? "lockstep" : "planned", t.shape ? "deep" : "wide", t.groups,
-                         t.per_wg, t.csplit, ms);
+                         t.sched == 2 ? "dataflow" : (t.sched ? "lockstep" : "planned"),
+                         t.shape ? "deep" : "wide", t.groups, t.per_wg, t.csplit, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = t;
@@ -551,7 +605,7 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
     // stage 1: schedule x shape (the rule's candidate last, so that whatever
     // still favours a later run favours the default)
     std::vector<BatchTune> stage1;
-    for (int sc : {0, 1})
+    for (int sc : {0, 1, 2})
         for (int sh : {0, 1}) {
             BatchTune t = rule;
             t.sched = sc;
@@ -565,9 +619,10 @@ jacobi_status run_batched(jacobi_ctx* c, int32_t count, const BatchItem* items, 
         jacobi_status st = trial(t);
         if (st != JACOBI_OK) return st;
     }
-    // stage 2: the lockstep schedule's grouping and item size
-    if (best.sched == 1) {
-        if (f_groups < 1) {
+    // stage 2: the lockstep schedule's grouping, and the item size of the
+    // lockstep and dataflow schedules
+    if (best.sched >= 1) {
+        if (f_groups < 1 && best.sched == 1) {
             BatchTune t = best;
             t.groups = kMaxGroups;
             jacobi_status st = trial(t);

@@ -1159,6 +1159,230 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Dataflow schedule (k_flow): the lockstep schedule's work items and row
+// sweep, without rounds.  Sweep r + 1 of a system needs only that system's
+// x^(r), so its items are queued the moment the last item of its sweep r
+// finishes: no workgroup waits at a grid barrier for systems it does not
+// touch, and the sweeps of different systems overlap.
+//
+// Queue: a sequence of work items.  Positions [0, nitems) are every system's
+// first work, item p at position p (the items are listed system by system,
+// largest system first); later positions are published in `ring` as
+// (gen << 32) | (item + 1).  A workgroup takes the next position with one
+// fetch-and-add on fhead and, if nothing is published there yet, waits for
+// it (or for the end of the run).  The system's `work` says what its queued
+// items do (2 r: sweep r; 2 r + 1: copy x^(r) to the caller's X); it changes
+// only when every item of the current work has finished.  Positions are
+// never reused within a launch (the host sizes the ring for every system's
+// max_iter works), so nothing is ever read stale.
+//
+// Completion: each item adds one to the system's `fin` with release order
+// after all of its stores; the item that completes the count takes an
+// acquire fence and runs the system's step: the stop test of sweep r (the
+// same test, from the same maximum or item-ordered sums, as the lockstep
+// schedule: the outcome does not depend on the schedule), then queues the
+// items of sweep r + 1 or of the copy-out, or, after a copy-out or on invalid
+// input, retires the system.  Publishing: `work`, the cleared statistics and
+// count, a release fence, then the ring entries; a claimer reads its entry
+// with acquire order.  The kernel ends when no system is left (`active`).
+// Deadlock freedom: a workgroup only waits for its own position to be
+// published, and while a system is active some item of it is running or its
+// next items are being published by a running workgroup.
+template <typename TA, int KT, int W, int TPW, int U, int MINB>
+__global__ __launch_bounds__(W * 64, MINB) void k_flow(BatchArgs p) {
+    using TX = typename IterOf<TA>::T;
+    constexpr int NT = KT / 16;
+    __shared__ TX red[W * TPW * NT * 256];
+    __shared__ uint64_t red_d[W], red_m[W];
+    __shared__ double red_s[W];
+    __shared__ int32_t s_item, s_work, s_bad;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    BCtl* ctl = p.ctl;
+    for (;;) {
+        __syncthreads();  // the shared words and red are reused
+        if (tid == 0) {
+            int32_t it = -1, work = 0, bad = 0;
+            const uint32_t pos =
+                __hip_atomic_fetch_add(&ctl->fhead, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t t_wait = 0;
+            for (;;) {
+                int32_t cand = -1;
+                if (pos < (uint32_t)p.nitems) {
+                    cand = (int32_t)pos;
+                } else if (pos - (uint32_t)p.nitems < p.ring_cap) {
+                    const uint64_t v = __hip_atomic_load(&p.ring[pos - (uint32_t)p.nitems],
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(v >> 32) == p.gen) cand = (int32_t)(uint32_t)v - 1;
+                }
+                if (cand >= 0) {
+                    it = cand;
+                    BState* st = &p.st[p.items[cand].sys];
+                    work = __hip_atomic_load(&st->work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (work == 2)
+                        bad = __hip_atomic_load(&st->bad_diag, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX ||
+                              __hip_atomic_load(&st->bad_rhs, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) != INT64_MAX;
+                    break;
+                }
+                // nothing published at this position yet: every remaining
+                // item is running, or the run is over
+                if (__hip_atomic_load(&ctl->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                        0 ||
+                    __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    break;
+                __builtin_amdgcn_s_sleep(8);
+                // a wait that cannot end becomes an error
+                const uint64_t now = wall_clock64();
+                if (t_wait == 0) {
+                    t_wait = now;
+                } else if ((int64_t)(now - t_wait) > p.spin_limit) {
+                    __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            s_item = it;
+            s_work = work;
+            s_bad = bad;
+        }
+        __syncthreads();
+        const int32_t it = s_item;
+        if (it < 0) break;
+        const int32_t work = s_work;
+        const BJob item = p.items[it];
+        BState* st = &p.st[item.sys];
+        const BSys S = p.sys[item.sys];
+        const int32_t r = work >> 1;
+        if (work & 1) {
+            // copy-out: this item's rows of x^(r) (r = 0: X0) into X
+            const TX* xsrc = (const TX*)((r & 1) ? S.buf1 : S.buf0);
+            const int k = S.k;
+            const int64_t ncopy = item.r1 - item.r0;
+            for (int64_t e = tid; e < ncopy * k; e += W * 64) {
+                const int64_t i = item.r0 + e / k;
+                const int c = (int)(e % k);
+                ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
+            }
+        } else if (!s_bad) {
+            // sweep r of this item's rows (x^(r-1) in buf[(r-1) & 1])
+            uint64_t dmax = 0, xmax = 0;
+            double sq = 0.0;
+            const TX* xin = (const TX*)((r & 1) ? S.buf0 : S.buf1);
+            TX* xout = (TX*)((r & 1) ? S.buf1 : S.buf0);
+            sweep_any<TA, KT, W, TPW, U>(S, item.r0, item.r1, xin, xout, red, tid, wave, dmax,
+                                         xmax, sq, 0, S.n, nullptr);
+            dmax = wmax(dmax);
+            xmax = wmax(xmax);
+            sq = wsum(sq);
+            if (lane == 0) {
+                red_d[wave] = dmax;
+                red_m[wave] = xmax;
+                red_s[wave] = sq;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t D = 0, M = 0;
+                double Q = 0.0;
+                for (int w = 0; w < W; ++w) {
+                    D = red_d[w] > D ? red_d[w] : D;
+                    M = red_m[w] > M ? red_m[w] : M;
+                    Q += red_s[w];
+                }
+                if (S.norm == 1)
+                    __hip_atomic_store(&p.item_parts[(size_t)(r & 1) * p.nitems + it], Q,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&st->dmax[r & 1], D, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&st->xmax[r & 1], M, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();  // every store of the item precedes thread 0's release
+        if (tid == 0) {
+            const uint32_t ni = (uint32_t)(S.it1 - S.it0);
+            const uint32_t f = __hip_atomic_fetch_add(&st->fin, 1u, __ATOMIC_RELEASE,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (f + 1 == ni) {
+                // the system's work is complete: its step
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                int32_t next = 0;  // work to queue (0: retire the system)
+                if (work & 1) {
+                    next = 0;
+                } else if (s_bad) {
+                    __hip_atomic_store(&st->done, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    const uint64_t D = __hip_atomic_load(&st->dmax[r & 1], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t M = __hip_atomic_load(&st->xmax[r & 1], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    double delta;
+                    if (S.norm == 1) {
+                        const double* ip = p.item_parts + (size_t)(r & 1) * p.nitems;
+                        double Q = 0.0;  // item order: independent of the schedule
+                        for (int32_t j = S.it0; j < S.it1; ++j)
+                            Q += __hip_atomic_load(&ip[j], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        delta = sqrt(Q);
+                    } else {
+                        delta = bitsd(D);
+                    }
+                    uint32_t flag = STOP_RUNNING;
+                    if (!isfinite(delta))
+                        flag = STOP_DIVERGED;
+                    else if (S.test == TEST_ABS ? (delta < S.tol) : (delta <= S.rel * bitsd(M)))
+                        flag = STOP_CONVERGED;
+                    if (flag != STOP_RUNNING || r == S.max_iter) {
+                        __hip_atomic_store(&st->status, flag, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->iterations, r, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->final_delta, dbits(delta), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->done, r + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        next = 2 * r + 1;
+                    } else {
+                        // sweep r + 1 accumulates in the other statistics slot
+                        __hip_atomic_store(&st->dmax[(r + 1) & 1], (uint64_t)0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->xmax[(r + 1) & 1], (uint64_t)0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        next = 2 * (r + 1);
+                    }
+                }
+                if (next == 0) {
+                    __hip_atomic_fetch_sub(&ctl->active, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    __hip_atomic_store(&st->work, next, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st->fin, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t q = __hip_atomic_fetch_add(&ctl->ftail, ni, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT) -
+                                       (uint32_t)p.nitems;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    for (uint32_t j = 0; j < ni; ++j) {
+                        if (q + j >= p.ring_cap) {
+                            // cannot happen with the host's sizing; end the launch
+                            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __hip_atomic_store(&p.ring[q + j],
+                                           ((uint64_t)p.gen << 32) | (uint32_t)(S.it0 + j + 1),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 constexpr int kBW = 4;   // waves per workgroup
 constexpr int kBU = 1;   // A blocks per pipeline stage (each block is two loads per row)
 
@@ -1166,19 +1390,29 @@ constexpr int kBU = 1;   // A blocks per pipeline stage (each block is two loads
 //   wide  two workgroups per CU; 4 tiles per pass for FP32 with <= 16 columns,
 //         else 2 (registers).  Many small systems: more workgroups to pack.
 //   deep  one workgroup per CU (the register file doubles, accumulators move
-//         to AGPRs) and 4 tiles per pass everywhere, so each B operand load
-//         serves 4 tiles.  Few large systems: less L2 traffic per A byte.
+//         to AGPRs) and 4 or 8 tiles per pass, so each B operand load serves
+//         4 or 8 tiles.  Few large systems: less L2 traffic per A byte.
 //   FP64 A takes 2 tiles per pass in the wide shape, 4 in the deep one.
+//   The deep lockstep kernel without column split (`wide8`) takes 8 tiles
+//   per pass for FP32 A and for BF16 A with <= 16 columns: each B operand
+//   load then serves 8 tiles (256 FP32 systems of 256..4096 rows, 32
+//   columns: 5.00 -> 4.70 ms; 64 systems of 4096 rows: 4.33 -> 4.82 TB/s).
+//   The planned and split kernels and BF16 with 32 columns would spill
+//   registers at 8, and the split plan cuts rows in ranges of 64 (one pass
+//   of 4 tiles), so they keep 4.
 template <typename TA>
-constexpr int tiles_per_pass(int kt, int variant) {
-    return (variant == 1 || (kt <= 16 && sizeof(TA) == 4)) ? 4 : 2;
+constexpr int tiles_per_pass(int kt, int variant, bool wide8 = false) {
+    if (variant == 1)
+        return (wide8 && (sizeof(TA) == 4 || (sizeof(TA) == 2 && kt <= 16))) ? 8 : 4;
+    return (kt <= 16 && sizeof(TA) == 4) ? 4 : 2;
 }
 
 // Shape parameters seen by the host planner: tiles per pass and the columns
 // one wave covers per pipeline round trip.
-int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant) {
-    if (a_dtype == 0) return tiles_per_pass<double>(kt, variant);
-    return a_dtype == 1 ? tiles_per_pass<float>(kt, variant) : tiles_per_pass<bf16_t>(kt, variant);
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant, bool lockstep_whole) {
+    if (a_dtype == 0) return tiles_per_pass<double>(kt, variant, lockstep_whole);
+    return a_dtype == 1 ? tiles_per_pass<float>(kt, variant, lockstep_whole)
+                        : tiles_per_pass<bf16_t>(kt, variant, lockstep_whole);
 }
 int batched_unroll(int32_t) { return 2 * kBU; }
 int batched_block_cols(int32_t a_dtype) {
@@ -1230,7 +1464,7 @@ hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BS
 template <typename TA, int KT, bool SPLIT>
 static const void* rounds_fn(int variant) {
     if (variant == 1)
-        return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 1), kBU, 1, SPLIT>;
+        return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 1, !SPLIT), kBU, 1, SPLIT>;
     return (const void*)k_rounds<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2, SPLIT>;
 }
 
@@ -1266,6 +1500,39 @@ int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus, bool 
 hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
                          hipStream_t s, bool split) {
     const void* fn = pick_rounds(a_dtype, kt, variant, split);
+    if (!fn) return hipErrorInvalidValue;
+    BatchArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBW * 64), args, 0, s);
+}
+
+template <typename TA, int KT>
+static const void* flow_fn(int variant) {
+    if (variant == 1)
+        return (const void*)k_flow<TA, KT, kBW, tiles_per_pass<TA>(KT, 1, true), kBU, 1>;
+    return (const void*)k_flow<TA, KT, kBW, tiles_per_pass<TA>(KT, 0), kBU, 2>;
+}
+
+static const void* pick_flow(int32_t a_dtype, int32_t kt, int variant) {
+    if (a_dtype == 0) return kt <= 16 ? flow_fn<double, 16>(variant) : flow_fn<double, 32>(variant);
+    if (a_dtype == 1) return kt <= 16 ? flow_fn<float, 16>(variant) : flow_fn<float, 32>(variant);
+    if (a_dtype == 2) return kt <= 16 ? flow_fn<bf16_t, 16>(variant) : flow_fn<bf16_t, 32>(variant);
+    return nullptr;
+}
+
+int flow_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus) {
+    const void* fn = pick_flow(a_dtype, kt, variant);
+    if (!fn) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBW * 64, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * num_cus;
+}
+
+hipError_t launch_flow(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
+                       hipStream_t s) {
+    const void* fn = pick_flow(a_dtype, kt, variant);
     if (!fn) return hipErrorInvalidValue;
     BatchArgs copy = a;
     void* args[] = {&copy};

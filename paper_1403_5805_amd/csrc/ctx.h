@@ -24,7 +24,7 @@ struct DevBuf {
 // Variant of a batched launch; every variant gives bitwise the same results.
 struct BatchTune {
     int shape = 1;   // 0 wide (two workgroups per CU), 1 deep (one)
-    int sched = 1;   // 0 planned, 1 lockstep
+    int sched = 1;   // 0 planned, 1 lockstep, 2 dataflow
     int groups = 1;  // lockstep: XCD groups of work items (1 = none)
     int per_wg = 8;  // lockstep: work items per workgroup and round
     int csplit = 1;  // lockstep, one system: column chunks (split-K); 1 = none
@@ -71,6 +71,9 @@ struct jacobi_ctx {
     bool tune_loaded = false;
     std::string tune_path;
     jac::DevBuf warm;
+    // dataflow schedule: queue ring (entries tagged with the launch's gen)
+    jac::DevBuf fring;
+    uint32_t flow_gen = 0;
 };
 
 namespace jac {

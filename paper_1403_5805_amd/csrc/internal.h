@@ -177,6 +177,9 @@ struct alignas(64) BState {
     int32_t done;            // lockstep schedule: 0 running, r + 1 stopped after sweep r
                              // (its X is copied out in round r + 1), -1 invalid input;
                              // the host sets 1 for max_iter = 0 (X0 copied out in round 1)
+    // dataflow schedule
+    uint32_t fin;            // items of the current work finished
+    int32_t work;            // current work: 2 r = sweep r, 2 r + 1 = copy x^(r) out to X
 };
 
 constexpr int kMaxGroups = 8;  // work-item groups of the lockstep schedule (XCDs)
@@ -197,6 +200,10 @@ struct alignas(64) BCtl {
     // work-item tickets of each group, by round parity: round r draws from
     // qhead[r & 1]; workgroup 0 clears the other parity during round r
     uint32_t qhead[2][kMaxGroups];
+    // dataflow schedule: queue positions [0, ftail) are reserved for
+    // publication (ftail starts at the item count), [0, fhead) are claimed
+    uint32_t ftail;
+    uint32_t fhead;
 };
 
 struct BatchArgs {
@@ -223,6 +230,12 @@ struct BatchArgs {
     int32_t nitems;
     int32_t active0;          // systems with max_iter > 0
     int32_t max_rounds;       // largest max_iter among them: the last round is max_rounds + 1
+    // dataflow schedule (k_flow): queue position q holds work item q for
+    // q < nitems (every system's first work), else ring[q - nitems] =
+    // (gen << 32) | (item + 1) once published
+    uint64_t* ring;
+    uint32_t ring_cap;        // entries of ring
+    uint32_t gen;             // this launch's tag (never 0)
 };
 
 hipError_t launch_batched_setup(int32_t a_dtype, int32_t kt, const BSys* sys, BState* st,
@@ -235,6 +248,11 @@ hipError_t launch_batched(int32_t a_dtype, int32_t kt, int variant, const BatchA
 hipError_t launch_rounds(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
                          hipStream_t s, bool split = false);
 int rounds_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus, bool split = false);
+// The dataflow schedule: no rounds; a system's next sweep (or its copy-out)
+// is queued as soon as the last item of its current one has finished.
+hipError_t launch_flow(int32_t a_dtype, int32_t kt, int variant, const BatchArgs& a, int grid,
+                       hipStream_t s);
+int flow_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 int batched_max_grid(int32_t a_dtype, int32_t kt, int variant, int num_cus);
 
 // ---------------------------------------------------------------------------
@@ -289,7 +307,7 @@ int resid_tiles(int32_t kt, int64_t n, int num_cus);
 hipError_t launch_resid_prep(int32_t kt, const RSys* sys, RState* st, int32_t count,
                              int64_t max_xld, hipStream_t s);
 hipError_t launch_resid(int32_t kt, int32_t tiles, const RArgs& a, int32_t jobs, hipStream_t s);
-int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant);
+int batched_tiles_per_pass(int32_t a_dtype, int32_t kt, int variant, bool lockstep_whole);
 int batched_unroll(int32_t a_dtype);
 int batched_block_cols(int32_t a_dtype);
 

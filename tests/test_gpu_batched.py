@@ -110,9 +110,11 @@ def test_kernel_shapes_bitwise(jac, dtype, monkeypatch):
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
 def test_schedules_bitwise(jac, dtype, monkeypatch):
     """The lockstep schedule (one sweep of every system per round, rows dealt
-    out as work items) and the planned one (split systems with their own
-    barriers, a queue of whole systems) give bitwise the same X and counts
-    under the maximum norm: a row's value does not depend on who sweeps it.
+    out as work items), the planned one (split systems with their own
+    barriers, a queue of whole systems) and the dataflow one (a system's next
+    sweep queued when its last item finishes, no rounds) give bitwise the
+    same X and counts under the maximum norm: a row's value does not depend
+    on who sweeps it.
     Covers max_iter = 0 (X = X0), a cap that stops every system, an invalid
     system among valid ones, and the Euclidean norm (counts and X equal, the
     distance to rounding)."""
@@ -134,24 +136,27 @@ def test_schedules_bitwise(jac, dtype, monkeypatch):
             (sysl, dict(tol=tol, max_iter=200, norm="l2"))]
     for r, (batch, kw) in enumerate(runs):
         out = {}
-        for sched in ("planned", "lockstep"):
+        for sched in ("planned", "lockstep", "dataflow"):
             monkeypatch.setenv("JACOBI_BATCHED_SCHED", sched)
             say("batched schedule", sched, dtype, r)
             out[sched] = jac.solve_batched(batch, **kw)
         monkeypatch.delenv("JACOBI_BATCHED_SCHED")
-        for i in range(len(shapes)):
-            a, b = out["planned"][1][i], out["lockstep"][1][i]
-            assert a["status"] == b["status"] and a["iterations"] == b["iterations"], (r, i, a, b)
-            if b["status"] < 0:
-                assert b["bad_index"] == a["bad_index"]
-                continue
-            assert torch.equal(out["planned"][0][i], out["lockstep"][0][i]), (r, shapes[i])
-            if kw.get("norm") == "l2":
-                assert b["final_delta"] == pytest.approx(a["final_delta"], rel=1e-12)
-            else:
-                assert b["final_delta"] == a["final_delta"]
-            if kw["max_iter"] == 0:
-                assert torch.equal(out["lockstep"][0][i], batch[i][2])
+        assert out["dataflow"][1][0]["kernel"] & 64 and out["lockstep"][1][0]["kernel"] & 1
+        for other in ("planned", "dataflow"):
+            for i in range(len(shapes)):
+                a, b = out[other][1][i], out["lockstep"][1][i]
+                assert a["status"] == b["status"] and a["iterations"] == b["iterations"], (
+                    other, r, i, a, b)
+                if b["status"] < 0:
+                    assert b["bad_index"] == a["bad_index"]
+                    continue
+                assert torch.equal(out[other][0][i], out["lockstep"][0][i]), (other, r, shapes[i])
+                if kw.get("norm") == "l2":
+                    assert b["final_delta"] == pytest.approx(a["final_delta"], rel=1e-12)
+                else:
+                    assert b["final_delta"] == a["final_delta"]
+                if kw["max_iter"] == 0:
+                    assert torch.equal(out[other][0][i], batch[i][2])
         if r == 3:
             assert out["lockstep"][1][3]["status"] == jac.ERR_NONFINITE_INPUT
 
@@ -237,7 +242,7 @@ def test_c3_scaled(jac):
         assert rel_err(host(xs[i]), xo) <= REL_F32
 
 
-def test_c3_full_size_properties(jac):
+def test_c3_full_size_properties(jac, monkeypatch):
     """The full batched workload (256 systems, n log-uniform in [256, 4096],
     k = 32): every system converges and satisfies the fixed-point property
     ||x - D^-1 (b - (A - D) x)||_inf <= 2 * Delta_final + O(u) (checked in FP64
@@ -272,6 +277,36 @@ def test_c3_full_size_properties(jac):
         xo, io = refs[i]
         assert abs(infos[i]["iterations"] - io["iterations"]) <= 1, (i, infos[i], io)
         assert rel_err(host(xs[i]), xo) <= REL_F32, i
+    # every schedule gives the same bits on the full workload
+    for sched in ("lockstep", "dataflow"):
+        monkeypatch.setenv("JACOBI_BATCHED_SCHED", sched)
+        say("c3 full", sched)
+        ys, yinfos = jac.solve_batched(sysl, tol=1e-6, max_iter=1000)
+        for i in range(len(ns)):
+            assert torch.equal(ys[i], xs[i]), (sched, i)
+            assert yinfos[i]["iterations"] == infos[i]["iterations"], (sched, i)
+    monkeypatch.delenv("JACOBI_BATCHED_SCHED")
+
+
+def test_dataflow_queue_cap_falls_back(jac, monkeypatch):
+    """The dataflow queue holds count x max_iter entries up to 32 Mi; a batch
+    whose sweep cap would need more runs the lockstep schedule instead (the
+    kernel code says which), with the same results."""
+    import torch
+    sysl = []
+    for idx in range(4):
+        A32, _, B32 = _sys32(200 + 50 * idx, 3, 3400 + idx)
+        sysl.append((dev(A32), dev(B32)))
+    monkeypatch.setenv("JACOBI_BATCHED_SCHED", "dataflow")
+    say("dataflow queue cap")
+    small, si = jac.solve_batched(sysl, tol=1e-6, max_iter=1000)
+    huge, hi = jac.solve_batched(sysl, tol=1e-6, max_iter=10_000_000)
+    monkeypatch.delenv("JACOBI_BATCHED_SCHED")
+    assert si[0]["kernel"] & 64 and not (si[0]["kernel"] & 1)
+    assert hi[0]["kernel"] & 1 and not (hi[0]["kernel"] & 64)
+    for a, b, ia, ib in zip(small, huge, si, hi):
+        assert ia["status"] == ib["status"] == jac.OK
+        assert torch.equal(a, b) and ia["iterations"] == ib["iterations"]
 
 
 def test_strided_out_with_x0(jac):
@@ -361,12 +396,14 @@ def test_f64_batch_parity(jac):
         assert rel_err(host(X), ref[4]) <= REL_F64, (n, k)
 
 
-def test_paper_workload_replay(jac):
+@pytest.mark.parametrize("sched", ["lockstep", "dataflow"])
+def test_paper_workload_replay(jac, sched, monkeypatch):
     """The shapes of the paper's serial timing table (n = 8 ... 512, FP64,
     one right-hand side) at its fixed L = 10000 sweeps (tol = 0) in one
     launch: every system runs exactly L sweeps and X agrees with the oracle's
     L sweeps to 1e-12.  The inputs are dominant systems (the paper's own
     U[0,1] inputs overflow long before L; see the next test)."""
+    monkeypatch.setenv("JACOBI_BATCHED_SCHED", sched)
     ns = [8, 16, 32, 64, 128, 256, 512]
     L = 10000
     sysl, refs = [], []
@@ -374,7 +411,7 @@ def test_paper_workload_replay(jac):
         A, _, B = synth.dominant(n, 1, 1600 + n, synth.ADDITIVE, 1.0, 2.0)
         sysl.append((dev(A), dev(B)))
         refs.append((A, B))
-    say("paper workload replay")
+    say("paper workload replay", sched)
     xs, infos = jac.solve_batched(sysl, tol=0.0, max_iter=L)
 
     def ref(r):
@@ -416,14 +453,17 @@ def test_paper_inputs_diverge_per_system(jac):
     assert torch.equal(alone[0], xs[-1]) and ia[0]["iterations"] == infos[-1]["iterations"]
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_many_small_systems_stop_in_different_rounds(jac, dtype):
+@pytest.mark.parametrize("dtype,sched", [("f32", "lockstep"), ("f64", "lockstep"),
+                                         ("f32", "dataflow"), ("f64", "dataflow")])
+def test_many_small_systems_stop_in_different_rounds(jac, dtype, sched, monkeypatch):
     """Hundreds of small systems (n = 1 ... 96) whose stop tests fire in
     different rounds, with max_iter = 0 systems and an invalid system among
-    them, solved five times in a row: every launch ends normally (no barrier
-    wait times out), every outcome is the one the system gets alone, and the
-    counts agree with the oracle's."""
+    them, solved five times in a row under the lockstep and the dataflow
+    schedules: every launch ends normally (no wait times out), every outcome
+    is the one the system gets alone, and the counts agree with the
+    oracle's."""
     import torch
+    monkeypatch.setenv("JACOBI_BATCHED_SCHED", sched)
     rng = np.random.default_rng(77)
     ns = rng.integers(1, 97, size=300)
     sysl, refs = [], []
@@ -438,7 +478,7 @@ def test_many_small_systems_stop_in_different_rounds(jac, dtype):
     bad[5] = (sysl[5][0], Bb)
     tol = 1e-11 if dtype == "f64" else 1e-6
     # tolerances spread the stop rounds: every third system runs a fixed count
-    say("many small systems", dtype)
+    say("many small systems", dtype, sched)
     first = None
     for rep in range(5):
         xs, infos = jac.solve_batched(bad, tol=tol, max_iter=60)
