@@ -114,8 +114,10 @@ typedef struct {
     double final_delta;       /* distance of the last executed sweep (-1 if none)        */
     double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */
     double device_ms;         /* device time of the whole call (HIP events)              */
-    double sweep_kernel_ms;   /* profile=1: summed duration of the sweep kernels         */
-    int64_t sweep_kernel_launches; /* profile=1: number of sweep kernels timed           */
+    double sweep_kernel_ms;   /* profile=1: summed duration of the sweep kernels;
+                                 batched-kernel solves: the persistent kernel's own
+                                 duration (setup excluded), always                       */
+    int64_t sweep_kernel_launches; /* number of sweep kernels timed (batched: 1)          */
 } jacobi_info;
 
 typedef struct jacobi_ctx jacobi_ctx;

@@ -96,6 +96,7 @@ jacobi_status ctx_init(jacobi_ctx* c, int device) {
     if (hipEventCreate(&c->ev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipEventCreate(&c->bev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipEventCreate(&c->bev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
+    if (hipEventCreate(&c->bev_kernel) != hipSuccess) return JACOBI_ERR_DEVICE;
     return JACOBI_OK;
 }
 
@@ -108,6 +109,7 @@ void ctx_release(jacobi_ctx* c) {
     c->stage.release();
     if (c->bev_begin) hipEventDestroy(c->bev_begin);
     if (c->bev_end) hipEventDestroy(c->bev_end);
+    if (c->bev_kernel) hipEventDestroy(c->bev_kernel);
     if (c->ctl) hipFree(c->ctl);
     if (c->slots) hipFree(c->slots);
     if (c->parts) hipFree(c->parts);

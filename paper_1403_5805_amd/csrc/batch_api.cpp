@@ -36,12 +36,14 @@ static double bits_to_double(uint64_t b) {
 }
 
 // Per-system outcomes from the device states after a launch.
-static void decode_states(const BState* hst, int32_t count, float ms, int32_t kernel,
-                          jacobi_info* infos) {
+static void decode_states(const BState* hst, int32_t count, float ms, float kernel_ms,
+                          int32_t kernel, jacobi_info* infos) {
     for (int i = 0; i < count; ++i) {
         jacobi_info& inf = infos[i];
         const BState& T = hst[i];
         inf.device_ms = ms;
+        inf.sweep_kernel_ms = kernel_ms;  // the persistent kernel alone
+        inf.sweep_kernel_launches = kernel_ms >= 0.f ? 1 : 0;
         inf.kernel = kernel;
         inf.rel_residual = -1.0;
         inf.bad_index = -1;
@@ -307,6 +309,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
     HIP_TRY(launch_copy16(c->stage.d, meta, up_b, s));
     HIP_TRY(hipEventRecord(c->bev_begin, s));
     HIP_TRY(launch_batched_setup(a_dtype, kt, d_sys, d_st, count, nmax, s));
+    HIP_TRY(hipEventRecord(c->bev_kernel, s));
     BatchArgs ba{};
     ba.sys = d_sys;
     ba.st = d_st;
@@ -357,9 +360,10 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         if (ctl.abort)  // a wait timed out: no outcome is trustworthy
             for (int i = 0; i < count; ++i) hst[i].error = 1;
     }
-    float ms = 0.f;
+    float ms = 0.f, kms = -1.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->bev_begin, c->bev_end));
-    decode_states(hst.data(), count, ms,
+    if (grid > 0) HIP_TRY(hipEventElapsedTime(&kms, c->bev_kernel, c->bev_end));
+    decode_states(hst.data(), count, ms, kms,
                   (sched == 1 ? 1 : 0) | (variant == 1 ? 2 : 0) | (sched == 2 ? 64 : 0) |
                       (sched == 1 ? (std::min(tune.groups, kMaxGroups) - 1) << 2 : 0) |
                       (sched >= 1 ? tune.per_wg << 8 : 0) | (csplit << 16),

@@ -689,6 +689,32 @@ __device__ __forceinline__ void sweep_any(const BSys& S, int64_t r0, int64_t r1,
                                       tid, wave, dmax, xmax, sq, c0, c1, (float*)part);
 }
 
+// Rows [r0, r1) of a final iterate (transposed: column c at xsrc + c * xld)
+// into the caller's row-major X, through an LDS tile of 64 rows (tile, the
+// row sweep's reduction area, holds 64 x (KT + 1) values): each column's run
+// of rows is read contiguously, each row's run of columns is written
+// contiguously.  Every thread of the workgroup calls it.
+template <typename TX, int KT, int W>
+__device__ __forceinline__ void copy_out(const BSys& S, int64_t r0, int64_t r1, const TX* xsrc,
+                                         TX* tile, int tid) {
+    constexpr int ROWS = 64, LD = KT + 1;  // odd stride: no bank conflicts either way
+    const int k = S.k;
+    TX* X = (TX*)S.X;
+    for (int64_t t0 = r0; t0 < r1; t0 += ROWS) {
+        const int nr = (int)(r1 - t0 < ROWS ? r1 - t0 : ROWS);
+        for (int e = tid; e < k * ROWS; e += W * 64) {
+            const int c = e / ROWS, i = e - c * ROWS;
+            if (i < nr) tile[i * LD + c] = xsrc[(int64_t)c * S.xld + t0 + i];
+        }
+        __syncthreads();
+        for (int e = tid; e < nr * k; e += W * 64) {
+            const int i = e / k, c = e - i * k;
+            X[(t0 + i) * S.ldx + c] = tile[i * LD + c];
+        }
+        __syncthreads();  // the tile is reused
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 //   W   waves per workgroup (they split the columns of every tile)
@@ -893,6 +919,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
     using TX = typename IterOf<TA>::T;
     constexpr int NT = KT / 16;
     __shared__ TX red[W * TPW * NT * 256];
+    static_assert(64 * (KT + 1) <= W * TPW * NT * 256, "the copy-out tile fits in red");
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ int32_t s_item, s_act;
@@ -1009,13 +1036,8 @@ __global__ __launch_bounds__(W * 64, MINB) void k_rounds(BatchArgs p) {
                 // stopped after sweep r - 1: this item's rows of the final
                 // iterate (one chunk of a split row range copies them)
                 const TX* xsrc = (const TX*)(((r - 1) & 1) ? S.buf1 : S.buf0);
-                const int k = S.k;
-                const int64_t ncopy = (SPLIT && item.rank != 0) ? 0 : item.r1 - item.r0;
-                for (int64_t e = tid; e < ncopy * k; e += W * 64) {
-                    const int64_t i = item.r0 + e / k;
-                    const int c = (int)(e % k);
-                    ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
-                }
+                if (!(SPLIT && item.rank != 0))
+                    copy_out<TX, KT, W>(S, item.r0, item.r1, xsrc, red, tid);
                 if (act == ACT_STOP && first && tid == 0) {
                     __hip_atomic_store(&st->status, s_flag, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1193,6 +1215,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_flow(BatchArgs p) {
     using TX = typename IterOf<TA>::T;
     constexpr int NT = KT / 16;
     __shared__ TX red[W * TPW * NT * 256];
+    static_assert(64 * (KT + 1) <= W * TPW * NT * 256, "the copy-out tile fits in red");
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ int32_t s_item, s_work, s_bad;
@@ -1260,13 +1283,7 @@ __global__ __launch_bounds__(W * 64, MINB) void k_flow(BatchArgs p) {
         if (work & 1) {
             // copy-out: this item's rows of x^(r) (r = 0: X0) into X
             const TX* xsrc = (const TX*)((r & 1) ? S.buf1 : S.buf0);
-            const int k = S.k;
-            const int64_t ncopy = item.r1 - item.r0;
-            for (int64_t e = tid; e < ncopy * k; e += W * 64) {
-                const int64_t i = item.r0 + e / k;
-                const int c = (int)(e % k);
-                ((TX*)S.X)[i * S.ldx + c] = xsrc[(int64_t)c * S.xld + i];
-            }
+            copy_out<TX, KT, W>(S, item.r0, item.r1, xsrc, red, tid);
         } else if (!s_bad) {
             // sweep r of this item's rows (x^(r-1) in buf[(r-1) & 1])
             uint64_t dmax = 0, xmax = 0;

@@ -60,7 +60,8 @@ struct jacobi_ctx {
     jac::DevBuf alo, diag_lo, xa, xb, r64, rlo, d0, d1, scal;
     // batched solver: per-system buffers and descriptors
     jac::DevBuf bws, bmeta;
-    hipEvent_t bev_begin = nullptr, bev_end = nullptr;  // batched launch timing
+    // batched launch timing: the call (setup included) and its persistent kernel
+    hipEvent_t bev_begin = nullptr, bev_kernel = nullptr, bev_end = nullptr;
     // batched FP64 residual: descriptors, transposed iterate, pinned outcomes
     jac::DevBuf rmeta, xT;
     // staging for descriptor uploads and outcome read-backs
