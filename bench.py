@@ -58,22 +58,37 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 # Fabric bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs
 # (each scaled by what the counter reads for a 1 GiB reference copy), valid
-# only for the kernel source with this sha256 prefix (profiles/ has the runs):
+# only for the kernel source whose code (its lines with `//` comments and blank
+# lines removed) has this sha256 prefix (profiles/ has the runs):
 # the FP32 sweep at n = 16384, and the batched launch of the 256-system
-# workload (deep shape, 16 items per workgroup).
-SWEEP_TRAFFIC = {"src": "sweep.hip", "sha256_prefix": "2a8f2d8cacc75a29", "n": 16384,
+# workload in the variant the counters measured (jacobi_info.kernel code:
+# dataflow schedule, deep shape, 4 items per workgroup).
+SWEEP_TRAFFIC = {"src": "sweep.hip", "code_sha256_prefix": "d38cdaa0a29e94f3", "n": 16384,
                  "bytes": 1074620084}
-C3_TRAFFIC = {"src": "batched.hip", "sha256_prefix": "5cf67cfd9905f68f", "bytes": 21110416755}
+C3_TRAFFIC = {"src": "batched.hip", "code_sha256_prefix": "5e0c38f69a73194a",
+              "bytes": 22361311751, "kernel": 64 | 2 | (4 << 8) | (1 << 16)}
+
+
+def _code_hash(path):
+    """sha256 prefix of a source's code: `//` comments and blank lines removed."""
+    import hashlib
+    import re
+    lines = []
+    with open(path) as f:
+        for ln in f.read().splitlines():
+            ln = re.sub(r"//.*$", "", ln).rstrip()
+            if ln.strip():
+                lines.append(ln)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
 def _traffic(rec):
-    import hashlib
     src = os.path.join(ROOT, "paper_1403_5805_amd", "csrc", rec["src"])
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = _code_hash(src)
     except OSError:
         return None
-    return rec["bytes"] if h == rec["sha256_prefix"] else None
+    return rec["bytes"] if h == rec["code_sha256_prefix"] else None
 
 
 def _sweep_traffic(n: int):
@@ -453,7 +468,7 @@ def bench_c3(args):
     res["step_ms"] = step_ms
     res["sweeps"] = [int(i["iterations"]) for i in infos][:8]
     code = infos[0]["kernel"]
-    measured = code == (1 | 2 | (16 << 8) | (1 << 16))  # the variant the counters measured
+    measured = code == C3_TRAFFIC["kernel"]  # the variant the counters measured
     res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                        "traffic": _traffic(C3_TRAFFIC) if measured else None,

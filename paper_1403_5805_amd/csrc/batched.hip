@@ -30,10 +30,12 @@
 //   * the diagonal term is masked in the A operand (sum over j != i);
 //   * the reduced tile is the epilogue's input: division by a_ii, the
 //     distance max|x_new - x_old| (or its Euclidean form) and the stop test.
-// Two schedules run the same row sweep (sweep_rows):
+// Three schedules run the same row sweep (sweep_rows):
 //   * lockstep (k_rounds, the default): round r is sweep r of every running
 //     system; rows of all systems are dealt out as work items from one
 //     atomic ticket counter, one grid barrier closes each round;
+//   * dataflow (k_flow): the same work items without rounds; a system's next
+//     sweep is queued the moment the last item of its current sweep ends;
 //   * planned (k_batched): a large system is split over several workgroups
 //     that meet at a per-system barrier (atomic counter) after every sweep;
 //     small systems are owned whole by one workgroup and taken from a queue.
