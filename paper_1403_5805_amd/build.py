@@ -25,7 +25,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch=
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 
-SOURCES = ["sweep.hip", "batched.hip", "resid.hip", "convert.hip", "api.cpp", "refine.cpp",
+SOURCES = ["sweep.hip", "batched.hip", "small.hip", "resid.hip", "convert.hip", "api.cpp",
+           "refine.cpp",
            "batch_api.cpp", "plan.cpp", "resid_api.cpp", "arena.cpp", "serve.cpp",
            "noalloc.cpp"]
 

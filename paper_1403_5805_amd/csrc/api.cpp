@@ -328,6 +328,49 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
     return solve_plain_vec(w, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, s, info);
 }
 
+// Small systems: every sweep in one persistent launch (k_small) instead of one
+// launch per sweep, whose launch cost exceeds such a sweep.  Used while A
+// holds at most 12 MiB and the iterate fits the kernel's LDS: measured per
+// solve (us, vector kernel / small kernel), FP64 n = 128: 151 / 99, n = 512:
+// 146 / 118, n = 1024: 181 / 161, n = 2048: 195 / 265; FP32 n = 2048: 155 /
+// 145, n = 3072: 177 / 220.  JACOBI_SMALL_MAX (rows) overrides the bound, 0
+// turns the kernel off; JACOBI_SMALL_ROWS sets the rows per workgroup.
+constexpr double kSmallMaxBytes = 12.0 * 1024 * 1024;
+
+static bool small_eligible(int32_t a_dtype, int64_t n, int kp) {
+    if (n > small_max_rows(a_dtype, kp)) return false;
+    if (const char* env = getenv("JACOBI_SMALL_MAX")) return n <= atoll(env);
+    return (double)n * (double)n * (double)dtype_bytes(a_dtype) <= kSmallMaxBytes;
+}
+
+static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, int kp,
+                               bool aligned, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
+                               double* delta_out, double* xmax_out) {
+    int64_t rows = 8;  // rows per workgroup (2 per wave)
+    if (const char* env = getenv("JACOBI_SMALL_ROWS")) rows = std::max<int64_t>(1, atoll(env));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(w.num_cus, (sa.n + rows - 1) / rows));
+    int rate_khz = 100000;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    sa.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
+    HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
+    HIP_TRY(hipMemcpyAsync(w.sc.h_ctl, w.sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const Ctl& h = *w.sc.h_ctl;
+    if (h.stop == STOP_TIMEOUT) {
+        set_error("a grid barrier wait of the small-system kernel timed out");
+        return JACOBI_ERR_INTERNAL;
+    }
+    *stop_out = h.stop;
+    *k_out = h.stop == STOP_INVALID ? 0 : (h.stop != STOP_RUNNING ? h.stop_sweep : sa.cap);
+    *delta_out = sa.cap > 0 ? bits_to_double(h.last_delta_bits) : -1.0;
+    *xmax_out = bits_to_double(h.last_xmax_bits);
+    return JACOBI_OK;
+}
+
 jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_dtype,
                               const void* A, int64_t lda, const void* B, int64_t ldb,
                               const void* X0, void* X, int64_t ldx, const jacobi_options& o,
@@ -368,8 +411,30 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
     int32_t K = 0;
     double delta = -1.0, xmax = 0.0, kms = 0.0;
     int64_t launches = 0;
-    jacobi_status st = run_sweeps(w.sc, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every,
-                                  o.profile, s, &stop, &K, &delta, &xmax, &kms, &launches);
+    jacobi_status st;
+    const bool small = o.profile == 0 && o.sync_every == 0 && small_eligible(a_dtype, n, kp);
+    if (small) {
+        SmallArgs sa{};
+        sa.A = A;
+        sa.lda = lda;
+        sa.B = B;
+        sa.ldb = ldb;
+        sa.diag = w.diag;
+        sa.n = n;
+        sa.k = (int32_t)k;
+        sa.cap = o.max_iter;
+        sa.buf0 = w.w0;
+        sa.buf1 = w.w1;
+        sa.ctl = ctl;
+        sa.slots = w.slots;
+        sa.parts = w.parts;
+        sa.tol = o.tol;
+        sa.norm = o.norm;
+        st = run_small(w, a_dtype, sa, kp, a.aligned != 0, s, &stop, &K, &delta, &xmax);
+    } else {
+        st = run_sweeps(w.sc, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every, o.profile, s,
+                        &stop, &K, &delta, &xmax, &kms, &launches);
+    }
     if (st != JACOBI_OK) return st;
     info->bad_index = -1;
     if (stop == STOP_INVALID) {
@@ -396,6 +461,7 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
     info->final_delta = K > 0 ? delta : -1.0;
     info->sweep_kernel_ms = kms;
     info->sweep_kernel_launches = launches;
+    info->kernel = small ? 128 : 0;
     jacobi_status res = JACOBI_NOT_CONVERGED;
     if (stop == STOP_CONVERGED) res = JACOBI_OK;
     if (stop == STOP_DIVERGED) res = JACOBI_DIVERGED;

@@ -13,7 +13,8 @@ enum : uint32_t {
     STOP_RUNNING = 0,
     STOP_CONVERGED = 1,  // distance met the test (or residual target reached)
     STOP_DIVERGED = 2,   // distance NaN/Inf
-    STOP_INVALID = 3     // validation failed: sweeps must not run
+    STOP_INVALID = 3,    // validation failed: sweeps must not run
+    STOP_TIMEOUT = 4     // a grid barrier wait of the small-system kernel timed out
 };
 
 // How the decider judges a sweep.
@@ -36,7 +37,7 @@ struct alignas(64) Ctl {
     int64_t bad_nonfinite;   // min row with non-finite alpha_ii   (INT64_MAX if none)
     int64_t bad_rhs;         // min row with non-finite B or X0    (INT64_MAX if none)
     uint32_t setup_ticket;
-    uint32_t pad1;
+    uint32_t bar;            // grid barrier arrivals of the small-system kernel (all sweeps)
 };
 
 // Per-launch reduction slot (three of them, launch seq uses slot seq % 3).
@@ -86,6 +87,35 @@ struct SweepArgs {
     int64_t ld_lo;
     int32_t lo_dtype;
 };
+
+// Arguments of the small-system kernel (k_small, small.hip): every sweep of
+// one system in one launch.  buf0 holds x^(0) (n x kp, row-major, from
+// k_setup), sweep r writes buf[r & 1]; slots and parts as for the vector
+// kernel; cap = max_iter.
+struct SmallArgs {
+    const void* A;
+    int64_t lda;
+    const void* B;     // TX, n x k (ldb)
+    int64_t ldb;
+    const void* diag;  // TX[n]
+    int64_t n;
+    int32_t k;
+    int32_t cap;
+    void* buf0;
+    void* buf1;
+    Ctl* ctl;
+    Slot* slots;       // [3]
+    double* parts;     // [3][kMaxParts]
+    double tol;        // TEST_ABS threshold
+    int32_t norm;      // 0 inf, 1 l2
+    int32_t pad;
+    int64_t spin_limit;  // wall-clock ticks before a barrier wait gives up
+};
+// Largest n whose iterate (n x kp of the launch's iterate type) fits the
+// kernel's LDS; grid <= resident workgroups (one per CU).
+int64_t small_max_rows(int32_t a_dtype, int32_t kp);
+hipError_t launch_small(int32_t a_dtype, const SmallArgs& a, int kp, bool aligned, int grid,
+                        hipStream_t s);
 
 // Host-side launch configuration chosen per call.
 struct LaunchCfg {

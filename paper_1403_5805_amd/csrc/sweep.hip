@@ -138,6 +138,7 @@ __global__ void k_init_ctl(Ctl* ctl, Slot* slots, int full) {
         ctl->sweeps_done = 0;
         ctl->last_delta_bits = dbits(-1.0);
         ctl->last_xmax_bits = 0;
+        ctl->bar = 0;
         if (full) {
             ctl->bad_zero = INT64_MAX;
             ctl->bad_nonfinite = INT64_MAX;

@@ -28,6 +28,7 @@ def test_c1_parity(jac):
     say("c1 n=512 f64")
     X, info = jac.solve(dev(A), dev(B), tol=1e-10, max_iter=1000)
     assert info["status"] == jac.OK, info
+    assert info["kernel"] == 128  # every sweep in one launch of the small-system kernel
     assert tie_margin(A, B, 1e-10, io["iterations"]) > 1e-6
     assert info["iterations"] == io["iterations"] == 9
     assert rel_err(host(X), xo) <= REL_F64
@@ -287,3 +288,60 @@ def test_c2_full_size_parity(jac):
     got = host(X1)[rows]
     assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
     del torch
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,k,pad", [(1, 1, 0), (5, 2, 0), (37, 2, 1), (512, 1, 0),
+                                     (1000, 2, 3), (2048, 1, 0), (2048, 2, 1)])
+def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
+    """Systems of at most 2048 rows (one or two right-hand sides) run every
+    sweep in one persistent launch, the small-system kernel; the per-sweep
+    vector kernel (JACOBI_SMALL_MAX=0) gives the same count and X to
+    rounding, and both agree with the oracle (FP64 to 1e-12 with the oracle's
+    count when the tie margin holds; FP32 and BF16 A to 1e-5 with the oracle
+    run in FP64 on the promoted system).  Rows that are not 16-byte aligned
+    (odd leading dimension) included; the Euclidean norm and the cap too."""
+    import torch
+    if dtype == "f64":
+        A, _, B = synth.dominant(n, k, 5100 + n + k)
+        Ap, Bp, tol, bar = A, B, 1e-11, REL_F64
+        tdt, vdt = torch.float64, torch.float64
+    else:
+        A32, _, B32 = synth.dominant_f32(n, k, 5100 + n + k, synth.ADDITIVE, 1.0, 2.0)
+        Ap = (torch.from_numpy(A32).to(torch.bfloat16).to(torch.float64).numpy()
+              if dtype == "bf16" else A32.astype(np.float64))
+        A, B, Bp, tol, bar = A32, B32, B32.astype(np.float64), 1e-6, REL_F32
+        tdt, vdt = (torch.bfloat16 if dtype == "bf16" else torch.float32), torch.float32
+    big = torch.zeros((n, n + pad), dtype=torch.float64)
+    big[:, :n] = torch.from_numpy(np.asarray(A, dtype=np.float64))
+    Ad = big.to(tdt).cuda()[:, :n]
+    Bd = torch.from_numpy(np.asarray(B)).to(vdt).cuda()
+    xo, io = oracle.jacobi(Ap, Bp, tol=tol, max_iter=500)
+    out = {}
+    for mode in ("small", "vector"):
+        # every size of this test fits the small kernel's LDS: force it, or turn it off
+        monkeypatch.setenv("JACOBI_SMALL_MAX", "4096" if mode == "small" else "0")
+        say("small-system kernel", dtype, n, k, pad, mode)
+        out[mode] = (jac.solve(Ad, Bd, tol=tol, max_iter=500),
+                     jac.solve(Ad, Bd, tol=0.0, max_iter=7, norm="l2"))
+    (Xs, inf_s), (Ls, linf_s) = out["small"]
+    (Xv, inf_v), (Lv, linf_v) = out["vector"]
+    assert inf_s["kernel"] == 128 and inf_v["kernel"] == 0
+    assert inf_s["status"] == inf_v["status"] == jac.OK, (inf_s, inf_v)
+    assert abs(inf_s["iterations"] - inf_v["iterations"]) <= (0 if dtype == "f64" else 1)
+    if dtype == "f64" and tie_margin(A, B, tol, io["iterations"]) > 1e-6:
+        assert inf_s["iterations"] == io["iterations"], (inf_s, io)
+    assert rel_err(host(Xs), xo) <= bar and rel_err(host(Xv), xo) <= bar
+    assert linf_s["iterations"] == linf_v["iterations"] == 7
+    assert linf_s["status"] == jac.NOT_CONVERGED
+    # the distance is a difference of consecutive iterates: it carries the
+    # iterate's absolute rounding, so it is compared at the X bar times max|x|
+    xm = float(np.abs(host(Ls)).max())
+    assert abs(linf_s["final_delta"] - linf_v["final_delta"]) <= bar * xm
+    xl, _ = oracle.jacobi(Ap, Bp, tol=0.0, max_iter=7, norm="l2")
+    assert rel_err(host(Ls), xl) <= bar
+    # the same inputs give the same bits again
+    monkeypatch.setenv("JACOBI_SMALL_MAX", "4096")
+    X2, inf2 = jac.solve(Ad, Bd, tol=tol, max_iter=500)
+    assert torch.equal(X2, Xs) and inf2["iterations"] == inf_s["iterations"]
+    monkeypatch.delenv("JACOBI_SMALL_MAX")
