@@ -545,7 +545,11 @@ def bench_c4(args, slow: bool = False):
     # reads A once and writes 2 bytes per value: counted as one residual pass
     # (8 n^2, in outer_iterations) plus the 2 n^2 written
     convert_b = 2 * n * n
-    tot_b = info["iterations"] * inner_b + info["outer_iterations"] * resid_b + convert_b
+    # every inner solve (one per outer step but the last) starts from d = 0:
+    # its first sweep is d = r / a_ii and reads no A_lo (only r, a_ii, d: 12 n)
+    solves = max(0, info["outer_iterations"] - 1)
+    tot_b = ((info["iterations"] - solves) * inner_b + solves * 12 * n +
+             info["outer_iterations"] * resid_b + convert_b)
     dev_ms = info["device_ms"]
     # the plain FP64 Jacobi solve stopped where its error is provably <= 1e-10
     tol64, q = _plain_tol(Ad, 1e-10 * xmax)

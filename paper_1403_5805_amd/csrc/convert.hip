@@ -105,6 +105,30 @@ __global__ void k_rhs_residual(const double* __restrict__ B, int64_t ldb, int64_
     }
 }
 
+// The first inner sweep from d = 0: every off-diagonal term multiplies zero,
+// so d^(1) = r / a_ii (the sweep's IEEE division of the same FP32 operands),
+// written without a pass over A_lo; padding columns [k, kp) are zero.
+__global__ void k_first_sweep(const float* __restrict__ rlo, const float* __restrict__ diag,
+                              int64_t n, int k, int64_t kp, float* __restrict__ d) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * kp; e += stride) {
+        const int64_t i = e / kp;
+        const int c = (int)(e % kp);
+        d[e] = c < k ? rlo[e] / diag[i] : 0.0f;
+    }
+}
+
+hipError_t launch_first_sweep(const float* rlo, const float* diag, int64_t n, int32_t k,
+                              int64_t kp, float* d, hipStream_t s) {
+    const int threads = 256;
+    int64_t blocks = (n * kp + threads - 1) / threads;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_first_sweep, dim3((unsigned)blocks), dim3(threads), 0, s, rlo, diag, n,
+                       k, kp, d);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs_residual(const double* B, int64_t ldb, int64_t n, int32_t k, int64_t kp,
                                double* r64, float* rlo, hipStream_t s) {
     const int threads = 256;

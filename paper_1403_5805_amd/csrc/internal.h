@@ -147,6 +147,10 @@ hipError_t launch_gather_diag(int32_t a_dtype, const void* A, int64_t lda, int64
                               void* out, hipStream_t s);
 hipError_t launch_bnorm(const double* B, int64_t ldb, int64_t n, int32_t k, double* out,
                         hipStream_t s);
+// d = r / a_ii (FP32, n x kp, padding zero): the refinement's first inner
+// sweep from d = 0, which needs no pass over A_lo.
+hipError_t launch_first_sweep(const float* rlo, const float* diag, int64_t n, int32_t k,
+                              int64_t kp, float* d, hipStream_t s);
 hipError_t launch_copy_rows(int32_t elem_bytes, const void* src, int64_t lds, void* dst,
                             int64_t ldd, int64_t n, int32_t k, hipStream_t s);
 hipError_t launch_zero_rows(int32_t elem_bytes, void* dst, int64_t ldd, int64_t n, int32_t k,

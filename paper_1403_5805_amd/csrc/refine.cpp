@@ -200,19 +200,30 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         return JACOBI_OK;
     };
     // Inner solve A_lo d = r from d = 0 (relative stop); d is left in *dout.
+    // Sweep 1 from d = 0 multiplies every off-diagonal entry by zero: d^(1) =
+    // r / a_ii, written by one elementwise kernel instead of a pass over A_lo
+    // (the same FP32 division, so the same values); it cannot meet the
+    // relative test (|d1 - 0| <= rel |d1| needs rel >= 1), and the sweeps go
+    // on from d^(1) and count it.
+    const bool first_free = o.inner_rel_tol < 1.0 && o.max_inner >= 2;
     auto inner_solve = [&](const float** dout, uint32_t* stop) -> jacobi_status {
+        if (first_free)
+            HIP_TRY(launch_first_sweep((const float*)c->rlo.p, (const float*)c->diag_lo.p, n,
+                                       (int)k, kp, (float*)c->d1.p, s));
+        const int32_t cap = first_free ? o.max_inner - 1 : o.max_inner;
         if (mfma_inner) {
-            BatchItem it{n, k, c->alo.p, ld_lo, c->rlo.p, kp, nullptr, c->d0.p, kp, o.max_inner};
+            BatchItem it{n,   k,  c->alo.p, ld_lo, c->rlo.p, kp, first_free ? c->d1.p : nullptr,
+                         c->d0.p, kp, cap};
             jacobi_options io;
             jacobi_options_default(&io);
             io.tol = 0.0;
-            io.max_iter = o.max_inner;
+            io.max_iter = cap;
             jacobi_info ii{};
             jacobi_status st =
                 run_batched(c, 1, &it, lo, io, TEST_REL, o.inner_rel_tol, s, &ii, true);
             if (st != JACOBI_OK) return st;
             if (ii.status < 0) return (jacobi_status)ii.status;
-            inner_total += ii.iterations;
+            inner_total += ii.iterations + (first_free ? 1 : 0);
             last_delta = ii.final_delta;
             *stop = ii.status == JACOBI_DIVERGED ? STOP_DIVERGED : STOP_RUNNING;
             *dout = (const float*)c->d0.p;
@@ -220,7 +231,7 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         }
         HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
         HIP_TRY(launch_zero_rows(4, c->d0.p, kp, n, kp, s));
-        HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
+        if (!first_free) HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
         SweepArgs ia{};
         ia.A = c->alo.p;
         ia.lda = ld_lo;
@@ -239,14 +250,15 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         ia.rel = o.inner_rel_tol;
         ia.norm = JACOBI_NORM_INF;
         ia.aligned = 1;
-        void* dbufs[2] = {c->d0.p, c->d1.p};
+        // the sweeps start from d^(1) in d1 (or from zero in d0)
+        void* dbufs[2] = {first_free ? c->d1.p : c->d0.p, first_free ? c->d0.p : c->d1.p};
         int32_t K = 0;
         double xmax = 0.0;
-        jacobi_status st = run_sweeps(sweep_ctl(c), lo, ia, icfg, dbufs, o.max_inner,
-                                      o.sync_every, o.profile, s, stop, &K, &last_delta, &xmax,
-                                      &kms, &launches);
+        jacobi_status st = run_sweeps(sweep_ctl(c), lo, ia, icfg, dbufs, cap, o.sync_every,
+                                      o.profile, s, stop, &K, &last_delta, &xmax, &kms,
+                                      &launches);
         if (st != JACOBI_OK) return st;
-        inner_total += K;
+        inner_total += K + (first_free ? 1 : 0);
         *dout = (const float*)dbufs[K & 1];
         return JACOBI_OK;
     };
