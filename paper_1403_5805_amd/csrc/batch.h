@@ -19,6 +19,12 @@ struct BatchItem {
     void* X;
     int64_t ldx;
     int32_t max_iter;
+    // 1: start from x^(1) = B / a_ii, the first sweep from x^(0) = 0 (which
+    // multiplies every off-diagonal entry by zero), computed by the setup
+    // kernel without a pass over A; X0 is ignored, max_iter counts the
+    // sweeps after it and the reported count excludes it.  For relative stop
+    // tests with rel < 1, which that first sweep can never meet.
+    int32_t first_free = 0;
 };
 
 // allow_split: a single system may have its columns split over workgroups

@@ -224,6 +224,7 @@ static jacobi_status run_batched_shape(jacobi_ctx* c, int32_t count, const Batch
         S.n = it.n;
         S.k = (int32_t)it.k;
         S.csplit = 1;
+        S.first_free = it.first_free;
         if (sched >= 1) {
             S.nwg = 1;
             S.it0 = ip.it0[i];

@@ -185,9 +185,15 @@ __global__ void k_batched_setup(const BSys* __restrict__ sys, BState* __restrict
         for (int c = 0; c < kt; ++c) {
             TX x0 = TX(0), b = TX(0);
             if (c < S.k) {
-                if (X0) x0 = X0[i * S.ldx + c];
                 b = B[i * S.ldb + c];
-                if (!isfinite(b) || !isfinite(x0)) bad = true;
+                if (S.first_free) {
+                    // the first sweep from zero: (b - 0) / a_ii, as the sweep's epilogue
+                    x0 = b / d;
+                    if (!isfinite(b)) bad = true;
+                } else {
+                    if (X0) x0 = X0[i * S.ldx + c];
+                    if (!isfinite(b) || !isfinite(x0)) bad = true;
+                }
             }
             buf0[c * S.xld + i] = x0;
             buf1[c * S.xld + i] = TX(0);

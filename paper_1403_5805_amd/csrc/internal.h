@@ -192,7 +192,7 @@ struct BSys {
     // chunk of a row range to finish adds them in chunk order.  csplit = 1:
     // no split.
     int32_t csplit;
-    int32_t pad;
+    int32_t first_free;  // 1: x^(0) := B / a_ii (the first sweep from zero, no pass over A)
     int64_t cw;
     void* part;
 };

@@ -207,13 +207,10 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     // on from d^(1) and count it.
     const bool first_free = o.inner_rel_tol < 1.0 && o.max_inner >= 2;
     auto inner_solve = [&](const float** dout, uint32_t* stop) -> jacobi_status {
-        if (first_free)
-            HIP_TRY(launch_first_sweep((const float*)c->rlo.p, (const float*)c->diag_lo.p, n,
-                                       (int)k, kp, (float*)c->d1.p, s));
         const int32_t cap = first_free ? o.max_inner - 1 : o.max_inner;
         if (mfma_inner) {
-            BatchItem it{n,   k,  c->alo.p, ld_lo, c->rlo.p, kp, first_free ? c->d1.p : nullptr,
-                         c->d0.p, kp, cap};
+            BatchItem it{n, k, c->alo.p, ld_lo, c->rlo.p, kp, nullptr, c->d0.p, kp, cap};
+            it.first_free = first_free ? 1 : 0;  // the setup kernel writes d^(1)
             jacobi_options io;
             jacobi_options_default(&io);
             io.tol = 0.0;
@@ -231,7 +228,11 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         }
         HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
         HIP_TRY(launch_zero_rows(4, c->d0.p, kp, n, kp, s));
-        if (!first_free) HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
+        if (first_free)
+            HIP_TRY(launch_first_sweep((const float*)c->rlo.p, (const float*)c->diag_lo.p, n,
+                                       (int)k, kp, (float*)c->d1.p, s));
+        else
+            HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
         SweepArgs ia{};
         ia.A = c->alo.p;
         ia.lda = ld_lo;

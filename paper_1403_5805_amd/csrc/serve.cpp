@@ -355,6 +355,11 @@ void compute_loop(jacobi_server* s) {
             }
         }
         // 3. One batched launch for every remaining inner solve, per sweep dtype.
+        // Each starts from d = 0, whose first sweep is d = r / a_ii: the setup
+        // kernel writes it (no pass over A_lo) and the sweeps go on from there
+        // (that sweep cannot meet the relative stop test when rel < 1).
+        const bool first_free = s->cfg.inner_rel_tol < 1.0 && s->cfg.inner_max >= 2;
+        const int32_t cap = first_free ? s->cfg.inner_max - 1 : s->cfg.inner_max;
         int64_t inner_sweeps = 0, inner_sys = 0;
         double inner_bytes = 0.0;
         for (int32_t lo : {JACOBI_F32, JACOBI_BF16}) {
@@ -363,7 +368,8 @@ void compute_loop(jacobi_server* s) {
             for (Req* q : keep) {
                 if (q->r.sweep_dtype != lo) continue;
                 BatchItem it{q->r.n, q->r.k, q->dAlo, q->ld_lo, q->rlo, q->kp, nullptr,
-                             q->d, q->kp, s->cfg.inner_max};
+                             q->d, q->kp, cap};
+                it.first_free = first_free ? 1 : 0;
                 items.push_back(it);
                 owners.push_back(q);
             }
@@ -372,7 +378,7 @@ void compute_loop(jacobi_server* s) {
             jacobi_options o;
             jacobi_options_default(&o);
             o.tol = 0.0;
-            o.max_iter = s->cfg.inner_max;
+            o.max_iter = cap;
             jacobi_status st = run_batched(s->ctx, (int32_t)items.size(), items.data(), lo, o,
                                            TEST_REL, s->cfg.inner_rel_tol, s->s_comp, infos.data());
             for (size_t i = 0; i < owners.size(); ++i) {
@@ -386,8 +392,8 @@ void compute_loop(jacobi_server* s) {
                     done_status.push_back(st != JACOBI_OK ? st : infos[i].status);
                     continue;
                 }
-                q->inner += infos[i].iterations;
-                inner_sweeps += infos[i].iterations;
+                q->inner += infos[i].iterations + (first_free ? 1 : 0);
+                inner_sweeps += infos[i].iterations + (first_free ? 1 : 0);
                 inner_sys += 1;
                 inner_bytes += (double)infos[i].iterations * (double)q->r.n * (double)q->r.n *
                                (lo == JACOBI_F32 ? 4.0 : 2.0);
