@@ -160,6 +160,37 @@ JACOBI_API jacobi_status jacobi_solve(jacobi_ctx* ctx, int64_t n, int64_t k,
                                       int64_t ldx, const jacobi_options* opt,
                                       hipStream_t stream, jacobi_info* info);
 
+/* ---------------------------------------------------------------------------
+ * Prepared matrices: one A solved repeatedly with new right-hand sides (the
+ * sec. 2 iteration on each).  jacobi_matrix_create keeps the caller's device
+ * pointer A (n x n, leading dimension lda; not copied: A must stay alive and
+ * unchanged until jacobi_matrix_destroy) and, with lo_dtype = JACOBI_F32 or
+ * JACOBI_BF16 (FP64 A only), builds once, in the handle's own device memory,
+ * the reduced-precision copy A_lo (round to nearest even) and its diagonal
+ * that REFINE solves would otherwise build on every call; lo_dtype = -1
+ * builds nothing.  It waits for `stream`.  Errors: INVALID_ARG (n < 1,
+ * lda < n, null A, bad dtype, a reduced copy of a non-FP64 A), OUT_OF_MEMORY,
+ * DEVICE; *out is then null.  The handle is bound to ctx (NULL: the default
+ * context) and its device. */
+typedef struct jacobi_matrix jacobi_matrix;
+
+JACOBI_API jacobi_status jacobi_matrix_create(jacobi_ctx* ctx, int64_t n, int32_t a_dtype,
+                                              const void* A, int64_t lda, int32_t lo_dtype,
+                                              hipStream_t stream, jacobi_matrix** out);
+
+/* jacobi_solve on the prepared A: the same arguments, checks, results (bitwise)
+ * and errors as jacobi_solve(ctx, n, k, a_dtype, A, lda, B, ...).  REFINE
+ * needs opt->sweep_dtype equal to the prepared lo_dtype (else INVALID_ARG) and
+ * then sweeps the prepared copy: no conversion pass over A. */
+JACOBI_API jacobi_status jacobi_solve_prepared(jacobi_matrix* m, int64_t k, const void* B,
+                                               int64_t ldb, const void* X0, void* X, int64_t ldx,
+                                               const jacobi_options* opt, hipStream_t stream,
+                                               jacobi_info* info);
+
+/* Free the handle and its device memory (NULL: no-op).  No solve on it may be
+ * running. */
+JACOBI_API jacobi_status jacobi_matrix_destroy(jacobi_matrix* m);
+
 /* One system of a batch (device pointers; same conventions as jacobi_solve). */
 typedef struct {
     int64_t n, k;       /* size and right-hand sides (k <= 32)                     */
@@ -230,7 +261,8 @@ typedef struct {
     double* X;                 /* HOST n x k FP64 output, leading dimension ldx               */
     int64_t ldx;
     int32_t sweep_dtype;       /* JACOBI_F32 or JACOBI_BF16 inner sweeps                      */
-    int32_t reserved;
+    int32_t max_outer;         /* refinement steps for this request (0 = the server's
+                                  max_outer); NOT_CONVERGED once it is exceeded             */
     double rel_tol;            /* stop when ||r||_2 < rel_tol * ||B||_2                       */
 } jacobi_request;
 

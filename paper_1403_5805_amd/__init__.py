@@ -20,8 +20,8 @@ from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVA
                    ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
                    F64, NOT_CONVERGED, OK, PENDING, Info, Options)
 
-__all__ = ["solve", "solve_noalloc", "solve_batched", "Batch", "Server", "status_string",
-           "last_error", "Context",
+__all__ = ["solve", "solve_noalloc", "solve_batched", "Batch", "Server", "Matrix",
+           "status_string", "last_error", "Context",
            "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
            "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
            "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
@@ -154,7 +154,7 @@ def _stream_handle(stream, device):
 
 
 def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
-          raise_on_error: bool = False, _noalloc: bool = False, **opts):
+          raise_on_error: bool = False, _noalloc: bool = False, _matrix=None, **opts):
     """Solve A X = B by Jacobi sweeps on the GPU.
 
     A: (n, n) torch tensor on the GPU, float64 / float32 / bfloat16, unit column
@@ -197,6 +197,8 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
         if ctx is not None:
             raise ValueError("the no-allocation entry point takes no context")
         st = lib.jacobi_solve_noalloc(*args)
+    elif _matrix is not None:
+        st = lib.jacobi_solve_prepared(_matrix.handle, *args[1:2], *args[5:])
     else:
         st = lib.jacobi_solve(ctx.handle if ctx else None, *args)
     d = info.as_dict()
@@ -216,6 +218,49 @@ def solve_noalloc(A, B, x0=None, *, out=None, stream=None, raise_on_error: bool 
     the result.  Same arguments and results as solve()."""
     return solve(A, B, x0, out=out, stream=stream, raise_on_error=raise_on_error,
                  _noalloc=True, **opts)
+
+
+class Matrix:
+    """A prepared matrix (jacobi_matrix_create): A kept for repeated solves
+    with new right-hand sides.  With sweep_dtype ("f32" | "bf16"; float64 A
+    only) the reduced-precision copy that refinement sweeps is built once, here,
+    instead of on every refine solve.  A must not change while the Matrix is
+    open.  solve() takes solve()'s arguments and gives the same results."""
+
+    def __init__(self, A, *, sweep_dtype: str | None = None, ctx: Context | None = None,
+                 stream=None):
+        lib = _lib.load()
+        if A.dim() != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError("A must be square")
+        n = A.shape[0]
+        dt = _a_dtype(A)
+        _check_operand(A, "A", A.device, A.dtype, (n, n))
+        lo = -1 if sweep_dtype is None else {"f32": F32, "bf16": BF16}[sweep_dtype]
+        h = ctypes.c_void_p()
+        st = lib.jacobi_matrix_create(ctx.handle if ctx else None, n, dt, _ptr(A), _ld(A), lo,
+                                      _stream_handle(stream, A.device), ctypes.byref(h))
+        if st != OK:
+            raise RuntimeError(f"jacobi_matrix_create: {status_string(st)} {last_error()}")
+        self.A, self.ctx, self.handle = A, ctx, h
+        _lib.track(self)
+
+    def solve(self, B, x0=None, *, out=None, stream=None, raise_on_error: bool = False,
+              **opts):
+        if not self.handle:
+            raise RuntimeError("the matrix is closed")
+        return solve(self.A, B, x0, out=out, ctx=self.ctx, stream=stream,
+                     raise_on_error=raise_on_error, _matrix=self, **opts)
+
+    def close(self):
+        if self.handle:
+            _lib.load().jacobi_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 from .batched import Batch, solve_batched  # noqa: E402

@@ -111,7 +111,7 @@ class Request(ctypes.Structure):
         ("X", ctypes.c_void_p),
         ("ldx", ctypes.c_int64),
         ("sweep_dtype", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32),
         ("rel_tol", ctypes.c_double),
     ]
 
@@ -191,6 +191,13 @@ def load():
                                          ctypes.POINTER(Options), vp, ctypes.POINTER(Info)]
     lib.jacobi_shutdown.restype = i32
     lib.jacobi_shutdown.argtypes = []
+    lib.jacobi_matrix_create.restype = i32
+    lib.jacobi_matrix_create.argtypes = [vp, i64, i32, vp, i64, i32, vp, ctypes.POINTER(vp)]
+    lib.jacobi_solve_prepared.restype = i32
+    lib.jacobi_solve_prepared.argtypes = [vp, i64, vp, i64, vp, vp, i64,
+                                          ctypes.POINTER(Options), vp, ctypes.POINTER(Info)]
+    lib.jacobi_matrix_destroy.restype = i32
+    lib.jacobi_matrix_destroy.argtypes = [vp]
     _lib = lib
     atexit.register(_shutdown)
     return lib

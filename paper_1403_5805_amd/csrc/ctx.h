@@ -151,8 +151,18 @@ size_t resid_xT_bytes(int64_t n, int64_t k);
 jacobi_status run_resid(jacobi_ctx* c, int32_t count, const ResidItem* items, hipStream_t s,
                         RState* out);
 
+// A reduced-precision copy of an FP64 A built ahead of the solves (a prepared
+// matrix): refinement then neither converts A nor gathers its diagonal.
+struct PreparedLo {
+    const void* alo;     // lo_dtype values, n x ld_lo
+    int64_t ld_lo;
+    const float* diag;   // diagonal of alo, widened to FP32
+    int32_t lo_dtype;    // JACOBI_F32 or JACOBI_BF16
+};
+
 jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, int64_t lda,
                            const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
-                           const jacobi_options& o, hipStream_t s, jacobi_info* info);
+                           const jacobi_options& o, hipStream_t s, jacobi_info* info,
+                           const PreparedLo* pre = nullptr);
 
 }  // namespace jac

@@ -47,16 +47,22 @@ static double bits_to_double(uint64_t b) {
 
 jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, int64_t lda,
                            const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
-                           const jacobi_options& o, hipStream_t s, jacobi_info* info) {
+                           const jacobi_options& o, hipStream_t s, jacobi_info* info,
+                           const PreparedLo* pre) {
     const int32_t lo = o.sweep_dtype;
     if ((lo != JACOBI_F32 && lo != JACOBI_BF16) || !(o.inner_rel_tol >= 0.0) ||
         !(o.refine_tol >= 0.0) || o.max_inner < 1 || o.max_outer < 0) {
         set_error("invalid refinement options");
         return JACOBI_ERR_INVALID_ARG;
     }
+    if (pre && pre->lo_dtype != lo) {
+        set_error("the matrix was prepared for another sweep dtype");
+        return JACOBI_ERR_INVALID_ARG;
+    }
     const int kp = kpad_of(k);
     const size_t elo = lo == JACOBI_F32 ? 4 : 2;
-    const int64_t ld_lo = (n + 7) / 8 * 8;  // 16-byte aligned rows for both FP32 and BF16
+    // 16-byte aligned rows for both FP32 and BF16 (or the prepared copy's)
+    const int64_t ld_lo = pre ? pre->ld_lo : (n + 7) / 8 * 8;
     HIP_TRY(c->diag.ensure(8 * n));
     HIP_TRY(c->xa.ensure(8 * n * kp));
     HIP_TRY(c->xb.ensure(8 * n * kp));
@@ -64,9 +70,13 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     HIP_TRY(c->rlo.ensure(4 * n * kp));
     HIP_TRY(c->d0.ensure(4 * n * kp));
     HIP_TRY(c->d1.ensure(4 * n * kp));
-    HIP_TRY(c->diag_lo.ensure(4 * n));
     HIP_TRY(c->scal.ensure(64));
-    HIP_TRY(c->alo.ensure(elo * (size_t)n * ld_lo));
+    if (!pre) {
+        HIP_TRY(c->diag_lo.ensure(4 * n));
+        HIP_TRY(c->alo.ensure(elo * (size_t)n * ld_lo));
+    }
+    void* const alo = pre ? const_cast<void*>(pre->alo) : c->alo.p;
+    float* const diag_lo = pre ? const_cast<float*>(pre->diag) : (float*)c->diag_lo.p;
     // Several right-hand sides: the residual runs on FP64 MFMA tiles and (from
     // 3 columns, as in the plain solve) the inner solve on the FP32 MFMA
     // kernel; one column streams through the vector kernels.
@@ -105,12 +115,12 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     // pass writes A_lo while it streams A (one read of the FP64 matrix
     // instead of two); the MFMA residual leaves it to the conversion kernel.
     const bool zero_start = X0 == nullptr;
-    bool fuse_convert = !mfma_resid && !zero_start;
+    bool fuse_convert = !pre && !mfma_resid && !zero_start;
     if (const char* env = getenv("JACOBI_REFINE_FUSED_CONVERT"))
         fuse_convert = fuse_convert && strcmp(env, "0") != 0;
-    if (!fuse_convert) {
-        HIP_TRY(launch_convert((const double*)A, lda, n, lo, c->alo.p, ld_lo, s));
-        HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
+    if (!pre && !fuse_convert) {
+        HIP_TRY(launch_convert((const double*)A, lda, n, lo, alo, ld_lo, s));
+        HIP_TRY(launch_gather_diag(lo, alo, ld_lo, n, diag_lo, s));
     }
     const LaunchCfg rcfg = residual_cfg(n, (int)k, c->num_cus);
     const LaunchCfg icfg = default_cfg(lo, n, (int)k, c->num_cus);
@@ -186,13 +196,13 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         ra.rlo = (float*)c->rlo.p;
         const bool write_lo = fuse_convert && outer == 0;
         if (write_lo) {
-            ra.alo = c->alo.p;
+            ra.alo = alo;
             ra.ld_lo = ld_lo;
             ra.lo_dtype = lo;
         }
         HIP_TRY(launch_residual(ra, rcfg, s));
         HIP_TRY(launch_decide(ra, rcfg.grid * (int)((k + 31) / 32), s));
-        if (write_lo) HIP_TRY(launch_gather_diag(lo, c->alo.p, ld_lo, n, c->diag_lo.p, s));
+        if (write_lo) HIP_TRY(launch_gather_diag(lo, alo, ld_lo, n, diag_lo, s));
         HIP_TRY(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *stop = c->h_ctl->stop;
@@ -209,7 +219,7 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
     auto inner_solve = [&](const float** dout, uint32_t* stop) -> jacobi_status {
         const int32_t cap = first_free ? o.max_inner - 1 : o.max_inner;
         if (mfma_inner) {
-            BatchItem it{n, k, c->alo.p, ld_lo, c->rlo.p, kp, nullptr, c->d0.p, kp, cap};
+            BatchItem it{n, k, alo, ld_lo, c->rlo.p, kp, nullptr, c->d0.p, kp, cap};
             it.first_free = first_free ? 1 : 0;  // the setup kernel writes d^(1)
             jacobi_options io;
             jacobi_options_default(&io);
@@ -229,16 +239,16 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
         HIP_TRY(launch_init_ctl(c->ctl, c->slots, 0, s));
         HIP_TRY(launch_zero_rows(4, c->d0.p, kp, n, kp, s));
         if (first_free)
-            HIP_TRY(launch_first_sweep((const float*)c->rlo.p, (const float*)c->diag_lo.p, n,
+            HIP_TRY(launch_first_sweep((const float*)c->rlo.p, diag_lo, n,
                                        (int)k, kp, (float*)c->d1.p, s));
         else
             HIP_TRY(launch_zero_rows(4, c->d1.p, kp, n, kp, s));
         SweepArgs ia{};
-        ia.A = c->alo.p;
+        ia.A = alo;
         ia.lda = ld_lo;
         ia.B = c->rlo.p;
         ia.ldb = kp;
-        ia.diag = c->diag_lo.p;
+        ia.diag = diag_lo;
         ia.n = n;
         ia.k = (int)k;
         ia.kpad = kp;

@@ -344,7 +344,7 @@ void compute_loop(jacobi_server* s) {
                 st = JACOBI_OK;
             else if (rst[i].stop == STOP_DIVERGED)
                 st = JACOBI_DIVERGED;
-            else if (q->outer > s->cfg.max_outer)
+            else if (q->outer > (q->r.max_outer > 0 ? q->r.max_outer : s->cfg.max_outer))
                 st = JACOBI_NOT_CONVERGED;
             if (st == JACOBI_PENDING) {
                 keep.push_back(q);
@@ -513,7 +513,7 @@ jacobi_status jacobi_serve_submit(jacobi_server* s, const jacobi_request* r, uin
         int32_t st = JACOBI_PENDING;
         if (n < 1 || k < 1 || k > 32 || r->lda < n || r->ldb < k || r->ldx < k || !r->A ||
             !r->B || !r->X || (r->sweep_dtype != JACOBI_F32 && r->sweep_dtype != JACOBI_BF16) ||
-            !(r->rel_tol >= 0.0) || n > (int64_t)INT32_MAX) {
+            !(r->rel_tol >= 0.0) || r->max_outer < 0 || n > (int64_t)INT32_MAX) {
             st = JACOBI_ERR_INVALID_ARG;
             set_error("invalid request");
         }

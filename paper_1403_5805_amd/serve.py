@@ -43,8 +43,9 @@ class Server:
         _lib.track(self)
 
     def submit(self, A: np.ndarray, B: np.ndarray, out: np.ndarray | None = None,
-               sweep_dtype: str = "bf16", rel_tol: float = 1e-12):
-        """Queue A x = B (host float64 arrays, B (n,) or (n, k)).  Returns
+               sweep_dtype: str = "bf16", rel_tol: float = 1e-12, max_outer: int = 0):
+        """Queue A x = B (host float64 arrays, B (n,) or (n, k)).  max_outer caps
+        this request's refinement steps (0: the server's cap).  Returns
         (ticket, status) where status is 0 when queued, else the error code."""
         A = np.ascontiguousarray(A, dtype=np.float64)
         if B.ndim not in (1, 2):
@@ -66,6 +67,7 @@ class Server:
         req.X, req.ldx = X.ctypes.data, k
         req.sweep_dtype = {"f32": 1, "bf16": 2}[sweep_dtype]
         req.rel_tol = rel_tol
+        req.max_outer = int(max_outer)
         t = ctypes.c_uint64()
         st = self._lib.jacobi_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t))
         with self._mu:

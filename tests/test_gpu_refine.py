@@ -285,3 +285,45 @@ def test_reduced_copy_rounding_bitwise(jac, fmt, n, k, pad, x0):
     x = host(X).reshape(n, k)
     bad = np.flatnonzero((x != np.asarray(xe).reshape(n, k)).any(axis=1))
     assert bad.size == 0, (fmt, bad[:8], x[bad[:4]], np.asarray(xe).reshape(n, k)[bad[:4]])
+
+
+@pytest.mark.parametrize("lo", ["bf16", "f32"])
+@pytest.mark.parametrize("n,k,x0", [(1500, 1, False), (1500, 1, True), (600, 4, False),
+                                    (333, 16, True)])
+def test_prepared_matrix(jac, lo, n, k, x0):
+    """A prepared matrix (jacobi_matrix_create) keeps A and, for refinement, its
+    reduced copy built once: every refine solve on it, for several right-hand
+    sides, equals jacobi_solve's refine solve of the same system bitwise (the
+    same rounding of A, built by the conversion kernel or by the fused first
+    residual pass), and so do plain solves; a sweep dtype other than the
+    prepared one, or a reduced copy of a non-FP64 matrix, is refused."""
+    import torch
+    A, Xt, B = synth.dominant(n, k, 4700 + n + k, synth.MULTIPLICATIVE, 0.5, 1.0)
+    Ad = dev(A)
+    m = jac.Matrix(Ad, sweep_dtype=lo)
+    xr = _xref(A, B)
+    for rep, scale in enumerate((1.0, -0.5, 2.0)):
+        Bd = dev(B * scale)
+        X0 = dev(np.random.default_rng(rep).uniform(-1, 1, size=B.shape)) if x0 else None
+        say("prepared matrix", lo, n, k, x0, rep)
+        Xp, ip = m.solve(Bd, X0, mode="refine", sweep_dtype=lo)
+        Xs, is_ = jac.solve(Ad, Bd, X0, mode="refine", sweep_dtype=lo)
+        assert ip["status"] == is_["status"] == jac.OK, (ip, is_)
+        assert torch.equal(Xp, Xs)
+        assert ip["iterations"] == is_["iterations"]
+        assert ip["outer_iterations"] == is_["outer_iterations"]
+        assert rel_err(host(Xp), xr * scale) <= REL_REFINE
+    Xp, ip = m.solve(dev(B), tol=1e-11, max_iter=500)
+    Xs, is_ = jac.solve(Ad, dev(B), tol=1e-11, max_iter=500)
+    assert ip["status"] == jac.OK and torch.equal(Xp, Xs) and ip["iterations"] == is_["iterations"]
+    other = "f32" if lo == "bf16" else "bf16"
+    _, bad = m.solve(dev(B), mode="refine", sweep_dtype=other)
+    assert bad["status"] == jac.ERR_INVALID_ARG
+    m.close()
+    with pytest.raises(RuntimeError):
+        jac.Matrix(Ad.float(), sweep_dtype=lo)
+    m32 = jac.Matrix(Ad.float())  # no reduced copy: plain solves only
+    X32, i32 = m32.solve(dev(B.astype(np.float32)), tol=1e-6, max_iter=500)
+    Y32, j32 = jac.solve(Ad.float(), dev(B.astype(np.float32)), tol=1e-6, max_iter=500)
+    assert torch.equal(X32, Y32) and i32["iterations"] == j32["iterations"]
+    m32.close()

@@ -90,6 +90,17 @@ def test_admission_rejection_and_errors(jac):
     assert st == jac.ERR_ZERO_DIAGONAL
     _, info = srv.poll(t)
     assert info["bad_index"] == 41
+    # a per-request cap on the refinement steps: stopped after its own cap, while
+    # the same request under the server's cap converges
+    t, st = srv.submit(A, B, sweep_dtype="bf16", rel_tol=1e-12, max_outer=1)
+    assert st == 0
+    X, info = srv.wait(t, timeout_s=120)
+    assert info["status"] == jac.NOT_CONVERGED and info["outer_iterations"] == 2, info
+    t, st = srv.submit(A, B, sweep_dtype="bf16", rel_tol=1e-12)
+    X, info = srv.wait(t, timeout_s=120)
+    assert info["status"] == jac.OK and info["outer_iterations"] > 2, info
+    t, st = srv.submit(A, B, max_outer=-1)
+    assert st == jac.ERR_INVALID_ARG
     srv.close()
 
 
