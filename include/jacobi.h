@@ -110,7 +110,8 @@ typedef struct {
                                  (lockstep), bits 8-15 work items per workgroup (lockstep,
                                  dataflow), bits 16+ column chunks of a split single system
                                  (1 = none); plain single solves: 128 when every sweep ran in
-                                 one launch of the small-system kernel, else 0              */
+                                 one launch of the small-system kernel, 129 when that was its
+                                 register-resident variant, else 0                          */
     int64_t bad_index;        /* first offending row for ZERO_DIAGONAL / NONFINITE, or -1 */
     double final_delta;       /* distance of the last executed sweep (-1 if none)        */
     double rel_residual;      /* REFINE: last ||r||_2/||B||_2; PLAIN: -1                 */

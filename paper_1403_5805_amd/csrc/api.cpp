@@ -92,6 +92,12 @@ jacobi_status ctx_init(jacobi_ctx* c, int device) {
         return JACOBI_ERR_OUT_OF_MEMORY;
     if (hipHostMalloc(&c->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
         return JACOBI_ERR_OUT_OF_MEMORY;
+    // the small-system kernel writes its outcome here directly when the
+    // mirror is mapped into the device's address space
+    if (hipHostGetDevicePointer((void**)&c->h_ctl_dev, c->h_ctl, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        c->h_ctl_dev = nullptr;
+    }
     if (hipEventCreate(&c->ev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipEventCreate(&c->ev_end) != hipSuccess) return JACOBI_ERR_DEVICE;
     if (hipEventCreate(&c->bev_begin) != hipSuccess) return JACOBI_ERR_DEVICE;
@@ -324,31 +330,67 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
     HIP_TRY(c->w0.ensure(sx * n * kp));
     HIP_TRY(c->w1.ensure(sx * n * kp));
     PlainWs w{sweep_ctl(c), c->slots, c->parts, c->diag.p, c->w0.p, c->w1.p,
-              c->ev_begin, c->ev_end, c->num_cus};
+              c->ev_begin, c->ev_end, c->num_cus, c->h_ctl_dev};
     return solve_plain_vec(w, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, s, info);
 }
 
-// Small systems: every sweep in one persistent launch (k_small) instead of one
-// launch per sweep, whose launch cost exceeds such a sweep.  Used while A
-// holds at most 12 MiB and the iterate fits the kernel's LDS: measured per
-// solve (us, vector kernel / small kernel), FP64 n = 128: 151 / 99, n = 512:
-// 146 / 118, n = 1024: 181 / 161, n = 2048: 195 / 265; FP32 n = 2048: 155 /
-// 145, n = 3072: 177 / 220.  JACOBI_SMALL_MAX (rows) overrides the bound, 0
-// turns the kernel off; JACOBI_SMALL_ROWS sets the rows per workgroup.
+// Small systems: every sweep in one persistent launch instead of one launch
+// per sweep, whose launch cost exceeds such a sweep.  The register-resident
+// variant (k_small_reg: each wave loads its rows of A once, then one memory
+// round trip per sweep) runs whenever every wave's rows fit its registers
+// with at most one workgroup per CU; otherwise the LDS variant (k_small: A
+// re-read every sweep) runs while A holds at most 12 MiB and the iterate
+// fits its LDS.  Measured per solve (us; register / LDS / per-sweep vector
+// kernel): FP64 n = 512: 99 / 118 / 154, n = 2048: 182 / 283 / 206; FP32
+// n = 2048: 141 / 167 / 171, n = 3072 (no register fit): - / 227 / 173;
+// BF16 n = 4096: 142 / 254 / 187.  JACOBI_SMALL_MAX (rows) overrides the
+// bound, 0 turns both off; JACOBI_SMALL_REG=0 keeps the LDS variant;
+// JACOBI_SMALL_ROWS sets the rows per workgroup.
 constexpr double kSmallMaxBytes = 12.0 * 1024 * 1024;
 
-static bool small_eligible(int32_t a_dtype, int64_t n, int kp) {
-    if (n > small_max_rows(a_dtype, kp)) return false;
-    if (const char* env = getenv("JACOBI_SMALL_MAX")) return n <= atoll(env);
-    return (double)n * (double)n * (double)dtype_bytes(a_dtype) <= kSmallMaxBytes;
+// Fewest workgroups with which every wave's rows of an n-row system fit the
+// register variant's registers, or 0 when they do not fit in max_grid.
+static int64_t small_reg_min_grid(int32_t a_dtype, int64_t n, int kp, int64_t max_grid,
+                                  int* np_out, int* rpw_out) {
+    const char* renv = getenv("JACOBI_SMALL_REG");
+    if (renv && atoi(renv) == 0) return 0;
+    const int np = small_reg_np(a_dtype, n);
+    const int rpw = np ? small_reg_rows_per_wave(a_dtype, kp, np) : 0;
+    if (rpw <= 0) return 0;
+    const int64_t need = std::max<int64_t>(1, (n + 4 * (int64_t)rpw - 1) / (4 * (int64_t)rpw));
+    if (need > max_grid) return 0;
+    if (np_out) *np_out = np;
+    if (rpw_out) *rpw_out = rpw;
+    return need;
 }
 
+static bool small_eligible(int32_t a_dtype, int64_t n, int kp, int num_cus) {
+    const char* env = getenv("JACOBI_SMALL_MAX");
+    if (env && n > atoll(env)) return false;
+    if (small_reg_min_grid(a_dtype, n, kp, std::min<int64_t>(num_cus, kMaxParts), nullptr,
+                           nullptr) > 0)
+        return true;
+    if (n > small_max_rows(a_dtype, kp)) return false;
+    return env || (double)n * (double)n * (double)dtype_bytes(a_dtype) <= kSmallMaxBytes;
+}
+
+// Launches the small-system kernel.  Unless sa.fused, also copies the control
+// block back, waits, and returns the outcome; a fused launch (register
+// variant only) writes its outcome to the host mirror and X itself, and the
+// caller waits.
 static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, int kp,
                                bool aligned, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
-                               double* delta_out, double* xmax_out) {
-    int64_t rows = 8;  // rows per workgroup (2 per wave)
+                               double* delta_out, double* xmax_out, bool* reg_out) {
+    const int64_t max_grid = std::min<int64_t>(w.num_cus, kMaxParts);
+    int np = 0, rpw = 0;
+    const int64_t reg_grid = small_reg_min_grid(a_dtype, sa.n, kp, max_grid, &np, &rpw);
+    const bool reg = reg_grid > 0;
+    // rows per workgroup: 16 (4 per wave) for the register variant, 8 for the
+    // LDS one, measured best at n = 512
+    int64_t rows = reg ? 16 : 8;
     if (const char* env = getenv("JACOBI_SMALL_ROWS")) rows = std::max<int64_t>(1, atoll(env));
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(w.num_cus, (sa.n + rows - 1) / rows));
+    int grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, (sa.n + rows - 1) / rows));
+    if (reg) grid = (int)std::max<int64_t>(grid, reg_grid);
     int rate_khz = 100000;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -356,7 +398,15 @@ static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, 
         rate_khz <= 0)
         rate_khz = 100000;
     sa.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
-    HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
+    sa.aligned = aligned ? 1 : 0;
+    if (sa.fused && !reg) return JACOBI_ERR_INTERNAL;  // the caller checked the fit
+    if (sa.fused) w.sc.h_ctl->timeout = 0;  // host write, before the launch
+    if (reg)
+        HIP_TRY(launch_small_reg(a_dtype, sa, kp, np, grid, s));
+    else
+        HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
+    *reg_out = reg;
+    if (sa.fused) return JACOBI_OK;
     HIP_TRY(hipMemcpyAsync(w.sc.h_ctl, w.sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const Ctl& h = *w.sc.h_ctl;
@@ -383,10 +433,24 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
         return JACOBI_ERR_INVALID_ARG;
     }
     Ctl* const ctl = w.sc.ctl;
+    const bool small =
+        o.profile == 0 && o.sync_every == 0 && small_eligible(a_dtype, n, kp, w.num_cus);
+    // Fused small solve: the register variant also takes the set-up's place
+    // and the copy-out, and leaves its outcome in the mapped host mirror:
+    // k_init_ctl and that launch, then one wait.  JACOBI_SMALL_FUSED=0 keeps
+    // the separate set-up, read-back and copy-out.
+    const char* fenv = getenv("JACOBI_SMALL_FUSED");
+    const bool x0_packed =
+        X0 == nullptr || (ldx == kp && (uintptr_t)X0 % 16 == 0);
+    const bool fused = small && o.max_iter >= 1 && w.h_ctl_dev != nullptr && x0_packed &&
+                       !(fenv && atoi(fenv) == 0) &&
+                       small_reg_min_grid(a_dtype, n, kp, std::min<int64_t>(w.num_cus, kMaxParts),
+                                          nullptr, nullptr) > 0;
     if (w.ev_begin) HIP_TRY(hipEventRecord(w.ev_begin, s));
     HIP_TRY(launch_init_ctl(ctl, w.slots, 1, s));
-    HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, w.diag, w.w0, w.w1,
-                         ctl, s));
+    if (!fused)
+        HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, w.diag, w.w0,
+                             w.w1, ctl, s));
     SweepArgs a{};
     a.A = A;
     a.lda = lda;
@@ -412,7 +476,7 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
     double delta = -1.0, xmax = 0.0, kms = 0.0;
     int64_t launches = 0;
     jacobi_status st;
-    const bool small = o.profile == 0 && o.sync_every == 0 && small_eligible(a_dtype, n, kp);
+    bool reg = false;
     if (small) {
         SmallArgs sa{};
         sa.A = A;
@@ -430,7 +494,52 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
         sa.parts = w.parts;
         sa.tol = o.tol;
         sa.norm = o.norm;
-        st = run_small(w, a_dtype, sa, kp, a.aligned != 0, s, &stop, &K, &delta, &xmax);
+        if (fused) {
+            sa.fused = 1;
+            sa.X0 = X0;
+            sa.ldx0 = ldx;
+            sa.X = X;
+            sa.ldx = ldx;
+            sa.hctl = w.h_ctl_dev;
+        }
+        st = run_small(w, a_dtype, sa, kp, a.aligned != 0, s, &stop, &K, &delta, &xmax, &reg);
+        if (st == JACOBI_OK && fused) {
+            if (w.ev_begin && w.ev_end) {
+                HIP_TRY(hipEventRecord(w.ev_end, s));
+                HIP_TRY(hipEventSynchronize(w.ev_end));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, w.ev_begin, w.ev_end));
+                info->device_ms = ms;
+            } else {
+                HIP_TRY(hipStreamSynchronize(s));
+                info->device_ms = -1.0;
+            }
+            const Ctl& h = *w.sc.h_ctl;
+            if (h.timeout != 0) {
+                set_error("a grid barrier wait of the small-system kernel timed out");
+                return JACOBI_ERR_INTERNAL;
+            }
+            info->bad_index = -1;
+            if (h.stop == STOP_INVALID) {
+                jacobi_status vs = validation_status(h, &info->bad_index);
+                info->status = vs;
+                info->iterations = 0;
+                info->final_delta = -1.0;
+                set_error("input validation failed at row %lld", (long long)info->bad_index);
+                return vs;
+            }
+            K = h.stop != STOP_RUNNING ? h.stop_sweep : o.max_iter;
+            info->iterations = K;
+            info->final_delta = bits_to_double(h.last_delta_bits);
+            info->sweep_kernel_ms = 0.0;
+            info->sweep_kernel_launches = 0;
+            info->kernel = 129;
+            jacobi_status res = JACOBI_NOT_CONVERGED;
+            if (h.stop == STOP_CONVERGED) res = JACOBI_OK;
+            if (h.stop == STOP_DIVERGED) res = JACOBI_DIVERGED;
+            info->status = res;
+            return res;
+        }
     } else {
         st = run_sweeps(w.sc, a_dtype, a, cfg, bufs, o.max_iter, o.sync_every, o.profile, s,
                         &stop, &K, &delta, &xmax, &kms, &launches);
@@ -461,7 +570,7 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
     info->final_delta = K > 0 ? delta : -1.0;
     info->sweep_kernel_ms = kms;
     info->sweep_kernel_launches = launches;
-    info->kernel = small ? 128 : 0;
+    info->kernel = small ? (reg ? 129 : 128) : 0;
     jacobi_status res = JACOBI_NOT_CONVERGED;
     if (stop == STOP_CONVERGED) res = JACOBI_OK;
     if (stop == STOP_DIVERGED) res = JACOBI_DIVERGED;

@@ -52,6 +52,7 @@ struct jacobi_ctx {
     jac::Slot* slots = nullptr;   // device reduction slots [3]
     double* parts = nullptr;      // device partial sums [3][kMaxParts]
     jac::Ctl* h_ctl = nullptr;    // pinned host mirror of ctl
+    jac::Ctl* h_ctl_dev = nullptr;  // its device-visible address (null: not mapped)
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     std::vector<hipEvent_t> prof_ev;
     // plain solve
@@ -112,6 +113,9 @@ struct PlainWs {
     void* w1;
     hipEvent_t ev_begin, ev_end;  // null: device_ms is not measured (-1)
     int num_cus;
+    // device-visible address of sc.h_ctl, or null (then the small-system
+    // kernel's outcome is copied back from sc.ctl)
+    Ctl* h_ctl_dev = nullptr;
 };
 
 // Padded column count of the iterate buffers for k right-hand sides.

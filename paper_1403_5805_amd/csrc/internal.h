@@ -30,7 +30,7 @@ struct alignas(64) Ctl {
     uint32_t stop;           // STOP_*
     int32_t stop_sweep;      // sweep number at which stop was decided
     int32_t sweeps_done;     // last sweep whose decision ran
-    int32_t pad0;
+    int32_t timeout;         // host mirror only: a barrier wait of k_small_reg timed out
     uint64_t last_delta_bits;  // double bits of the last decided distance
     uint64_t last_xmax_bits;   // double bits of max|x_new| of the last sweep
     int64_t bad_zero;        // min row with alpha_ii == 0         (INT64_MAX if none)
@@ -108,14 +108,31 @@ struct SmallArgs {
     double* parts;     // [3][kMaxParts]
     double tol;        // TEST_ABS threshold
     int32_t norm;      // 0 inf, 1 l2
-    int32_t pad;
+    int32_t aligned;   // rows of A 16-byte aligned (k_small_reg's one-time load)
     int64_t spin_limit;  // wall-clock ticks before a barrier wait gives up
+    // k_small_reg only, fused = 1: the kernel also takes the set-up's place
+    // (a_ii from A, x^(0) read from X0 or zero, the input checks) and writes
+    // X itself; hctl (if not null, device-visible host memory) receives the
+    // final control block.  Needs cap >= 1.
+    int32_t fused;
+    int32_t pad2;
+    const void* X0;    // TX, n x k packed (ldx0 = k, 16-byte aligned), or null: x^(0) = 0
+    int64_t ldx0;
+    void* X;           // TX, n x k (ldx)
+    int64_t ldx;
+    Ctl* hctl;
 };
 // Largest n whose iterate (n x kp of the launch's iterate type) fits the
 // kernel's LDS; grid <= resident workgroups (one per CU).
 int64_t small_max_rows(int32_t a_dtype, int32_t kp);
 hipError_t launch_small(int32_t a_dtype, const SmallArgs& a, int kp, bool aligned, int grid,
                         hipStream_t s);
+// Register-resident variant (k_small_reg): np = 16-byte pieces per lane and
+// row (a power of two, 0 if n needs more than 16), rows per wave it holds.
+int small_reg_np(int32_t a_dtype, int64_t n);
+int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np);
+hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int grid,
+                            hipStream_t s);
 
 // Host-side launch configuration chosen per call.
 struct LaunchCfg {

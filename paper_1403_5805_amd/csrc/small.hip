@@ -258,6 +258,492 @@ __global__ __launch_bounds__(256) void k_small(SmallArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant.  A does not change between sweeps and wave w of
+// workgroup g always owns the same rows (w + 4 g + 4 G t), so the wave loads
+// its rows once, before the first sweep, into registers: one 16-byte piece
+// of a row per lane and step of 64 pieces (NP steps cover the row), the
+// diagonal entry stored as zero, and b_i, a_ii beside them.  Every sweep
+// then reads only the iterate, straight into registers (a lane needs the
+// same NP pieces of x for every row it holds), all loads issued before the
+// first use: one memory round trip per sweep instead of one per piece.  The
+// products, their order, the lane sums, the update and the statistics are
+// those of k_small, so both kernels give the same bits.
+
+// Rows per wave (at most 8) that a budget of 192 32-bit registers per lane
+// holds beside the iterate's pieces, 0 if not one row fits.
+template <typename TA, typename TX, int KP, int NP>
+constexpr int small_reg_rpw() {
+    constexpr int V = Piece<TA, TX>::V;
+    constexpr int xv = NP * V * KP * (int)sizeof(TX) / 4;
+    constexpr int r = (192 - xv) / (4 * NP);
+    return r < 1 ? 0 : (r > 8 ? 8 : r);
+}
+
+template <typename TA, typename TX>
+__device__ __forceinline__ u32x4 pack_piece(const TX* v);
+template <>
+__device__ __forceinline__ u32x4 pack_piece<double, double>(const double* v) {
+    u32x4 u;
+    u.x = (uint32_t)__double2loint(v[0]);
+    u.y = (uint32_t)__double2hiint(v[0]);
+    u.z = (uint32_t)__double2loint(v[1]);
+    u.w = (uint32_t)__double2hiint(v[1]);
+    return u;
+}
+template <>
+__device__ __forceinline__ u32x4 pack_piece<float, float>(const float* v) {
+    u32x4 u;
+    u.x = __float_as_uint(v[0]);
+    u.y = __float_as_uint(v[1]);
+    u.z = __float_as_uint(v[2]);
+    u.w = __float_as_uint(v[3]);
+    return u;
+}
+template <>
+__device__ __forceinline__ u32x4 pack_piece<bf16_t, float>(const float* v) {
+    // every value came from a BF16 (low 16 bits zero): the pair packs exactly
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        w[e] = (__float_as_uint(v[2 * e]) >> 16) | (__float_as_uint(v[2 * e + 1]) & 0xffff0000u);
+    u32x4 u;
+    u.x = w[0];
+    u.y = w[1];
+    u.z = w[2];
+    u.w = w[3];
+    return u;
+}
+
+// The inverse of pack_piece: the V values of a held piece, widened.
+template <typename TA, typename TX>
+__device__ __forceinline__ void unpack_piece(const u32x4 u, TX* v);
+template <>
+__device__ __forceinline__ void unpack_piece<double, double>(const u32x4 u, double* v) {
+    v[0] = __hiloint2double((int)u.y, (int)u.x);
+    v[1] = __hiloint2double((int)u.w, (int)u.z);
+}
+template <>
+__device__ __forceinline__ void unpack_piece<float, float>(const u32x4 u, float* v) {
+    v[0] = __uint_as_float(u.x);
+    v[1] = __uint_as_float(u.y);
+    v[2] = __uint_as_float(u.z);
+    v[3] = __uint_as_float(u.w);
+}
+template <>
+__device__ __forceinline__ void unpack_piece<bf16_t, float>(const u32x4 u, float* v) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[2 * e] = __uint_as_float(w[e] << 16);
+        v[2 * e + 1] = __uint_as_float(w[e] & 0xffff0000u);
+    }
+}
+
+template <typename TA, typename TX, int KP, int NP>
+__global__ __launch_bounds__(256) void k_small_reg(SmallArgs a) {
+    constexpr int W = 4;
+    constexpr int V = Piece<TA, TX>::V;
+    constexpr int RPW = small_reg_rpw<TA, TX, KP, NP>();
+    __shared__ uint64_t red_d[W], red_m[W];
+    __shared__ double red_s[W];
+    __shared__ uint32_t s_go, s_stop;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = (int)gridDim.x;
+    const int64_t n = a.n;
+    const int k = a.k;
+    const TA* A = (const TA*)a.A;
+    const TX* B = (const TX*)a.B;
+    const TX* diag = (const TX*)a.diag;
+    Ctl* ctl = a.ctl;
+    if (tid == 0)
+        s_go = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               STOP_RUNNING;
+    __syncthreads();
+    if (!s_go) return;  // invalid input: no sweep
+    const int64_t i0 = wave + (int64_t)W * blockIdx.x;
+    const int64_t di = (int64_t)W * G;
+    // rows t < nr of this wave; the host guarantees nr <= RPW
+    const int nr = i0 < n ? (int)((n - i0 + di - 1) / di) : 0;
+    u32x4 ar[RPW][NP];
+    TX br[RPW], dr[RPW];
+    // every 16-byte piece of the wave's rows in flight at once
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+        const int64_t i = i0 + di * t;
+        br[t] = TX(0);
+        dr[t] = TX(1);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int64_t c0 = ((int64_t)lane + 64 * p) * V;
+            ar[t][p] = u32x4{0u, 0u, 0u, 0u};
+            if (t < nr && a.aligned != 0 && c0 + V <= n)
+                ar[t][p] = *(const u32x4*)(A + i * a.lda + c0);
+        }
+        if (t < nr && lane < k) {
+            br[t] = B[i * a.ldb + lane];
+            if (a.fused) {
+                TX v1[V];  // a_ii, widened as the set-up kernel does
+                Piece<TA, TX>::load(A + i * a.lda + i, false, 0, 1, v1);
+                dr[t] = v1[0];
+            } else {
+                dr[t] = diag[i];
+            }
+        }
+    }
+    // the piece that ends a row, and every piece of rows that are not
+    // 16-byte aligned, element by element
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+        const int64_t i = i0 + di * t;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int64_t c0 = ((int64_t)lane + 64 * p) * V;
+            if (t < nr && c0 < n && !(a.aligned != 0 && c0 + V <= n)) {
+                TX v[V];
+                Piece<TA, TX>::load(A + i * a.lda + c0, false, c0, n, v);
+                ar[t][p] = pack_piece<TA, TX>(v);
+            }
+        }
+    }
+    // the diagonal term is skipped: held as zero (one lane and piece per row)
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+        const int64_t i = i0 + di * t;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int64_t c0 = ((int64_t)lane + 64 * p) * V;
+            if (t < nr && c0 <= i && i < c0 + V) {
+                TX v[V];
+                unpack_piece<TA, TX>(ar[t][p], v);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (c0 + e == i) v[e] = TX(0);
+                ar[t][p] = pack_piece<TA, TX>(v);
+            }
+        }
+    }
+    // Iteration r loads x^(r-1), then takes the stop decision of sweep r - 1
+    // (its statistics were final at barrier r - 1, whose acquire thread 0
+    // has taken), so that their two loads overlap; iteration cap + 1 only
+    // decides.  A stop discards the loads of x.  Fused (set-up and copy-out
+    // in this launch): sweep 1 reads x^(0) from X0 (or takes zero) and checks
+    // the rows' a_ii, b and x^(0) as the set-up kernel does; the decision of
+    // sweep 1 sees the outcome of every workgroup's checks (they precede
+    // barrier 1) and stops with STOP_INVALID before anything is written to X;
+    // the final decision has each wave write its rows of X from registers.
+    TX xl[RPW];  // the rows' components of the wave's last sweep (lanes c < k)
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) xl[t] = TX(0);
+    int64_t bad_z = INT64_MAX, bad_n = INT64_MAX, bad_r = INT64_MAX;  // thread 0
+    for (int r = 1;; ++r) {
+        const bool sweep = r <= a.cap;
+        // fused sweep 1 reads x^(0) from X0 (n x k, packed), null for zero
+        const TX* xin = (a.fused && r == 1) ? (const TX*)a.X0
+                                            : (const TX*)((r & 1) ? a.buf0 : a.buf1);
+        TX* xout = (TX*)((r & 1) ? a.buf1 : a.buf0);
+        // the lane's pieces of x^(r-1) (columns (lane + 64 p) V ...) and, for
+        // lanes c < k, the old value of its rows' component c
+        TX xv[NP][V * KP];
+        TX xo[RPW];
+        if (sweep && xin == nullptr) {
+            // fused, x^(0) = 0
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int e = 0; e < V * KP; ++e) xv[p][e] = TX(0);
+#pragma unroll
+            for (int t = 0; t < RPW; ++t) xo[t] = TX(0);
+        } else if (sweep) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int64_t c0 = ((int64_t)lane + 64 * p) * V;
+                if (c0 + V <= n) {
+#pragma unroll
+                    for (int q = 0; q < V * KP * (int)sizeof(TX) / 16; ++q) {
+                        const u32x4 u = *(const u32x4*)(xin + c0 * KP + q * (16 / sizeof(TX)));
+                        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+                        if constexpr (sizeof(TX) == 8) {
+                            xv[p][2 * q] = __hiloint2double((int)w[1], (int)w[0]);
+                            xv[p][2 * q + 1] = __hiloint2double((int)w[3], (int)w[2]);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) xv[p][4 * q + e] = __uint_as_float(w[e]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < V * KP; ++e)
+                        xv[p][e] = c0 + e / KP < n ? xin[c0 * KP + e] : TX(0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < RPW; ++t)
+                xo[t] = (t < nr && lane < k) ? xin[(i0 + di * t) * KP + lane] : TX(0);
+        }
+        if (r > 1) {
+            if (tid == 0) {
+                const int q = r - 1;
+                const Slot* sl = &a.slots[q % 3];
+                uint32_t st = STOP_RUNNING;
+                const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT));
+                const double xm = bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT));
+                double delta = dm;
+                if (a.norm == 1) {
+                    double S = 0.0;  // workgroup order
+                    for (int g = 0; g < G; ++g)
+                        S += __hip_atomic_load(&a.parts[(size_t)(q % 3) * kMaxParts + g],
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    delta = sqrt(S);
+                }
+                if (!isfinite(delta))
+                    st = STOP_DIVERGED;
+                else if (delta < a.tol)
+                    st = STOP_CONVERGED;
+                if (a.fused && q == 1) {
+                    bad_z = __hip_atomic_load(&ctl->bad_zero, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    bad_n = __hip_atomic_load(&ctl->bad_nonfinite, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    bad_r = __hip_atomic_load(&ctl->bad_rhs, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    if (bad_z != INT64_MAX || bad_n != INT64_MAX || bad_r != INT64_MAX)
+                        st = STOP_INVALID;
+                }
+                if (blockIdx.x == 0) {
+                    __hip_atomic_store(&ctl->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ctl->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ctl->sweeps_done, q, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    if (st != STOP_RUNNING) {
+                        __hip_atomic_store(&ctl->stop_sweep, q, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&ctl->stop, st, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    Ctl* h = a.hctl;
+                    if (h != nullptr && (st != STOP_RUNNING || !sweep)) {
+                        // the final control block, straight to the host
+                        __hip_atomic_store(&h->stop, st, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->stop_sweep, st != STOP_RUNNING ? q : 0,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->sweeps_done, q, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->bad_zero, bad_z, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->bad_nonfinite, bad_n, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&h->bad_rhs, bad_r, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
+                }
+                s_go = st == STOP_RUNNING;
+                s_stop = st;
+            }
+            __syncthreads();
+            if (!s_go || !sweep) {
+                const uint32_t st = s_stop;
+                if (a.fused && st != STOP_INVALID && st != STOP_TIMEOUT && lane < k) {
+                    TX* X = (TX*)a.X;
+#pragma unroll
+                    for (int t = 0; t < RPW; ++t)
+                        if (t < nr) X[(i0 + di * t) * a.ldx + lane] = xl[t];
+                }
+                break;
+            }
+        }
+        if (!sweep) break;
+        uint64_t dmax = 0, xmax = 0;
+        double sq = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPW; ++t) {
+            if (t >= nr) break;
+            const int64_t i = i0 + di * t;
+            TX s[KP];
+#pragma unroll
+            for (int c = 0; c < KP; ++c) s[c] = TX(0);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int64_t c0 = ((int64_t)lane + 64 * p) * V;
+                if (c0 < n) {
+                    TX v[V];
+                    u32x4 u = ar[t][p];
+                    // BF16: unpack in every sweep; hoisted out of the loop,
+                    // the widened values would take twice the registers
+                    if constexpr (sizeof(TA) == 2) asm volatile("" : "+v"(u));
+                    unpack_piece<TA, TX>(u, v);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        if (c0 + e < n) {
+#pragma unroll
+                            for (int c = 0; c < KP; ++c) s[c] += v[e] * xv[p][e * KP + c];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < KP; ++c) s[c] = lane_sum(s[c]);
+            if (lane < k) {
+                TX sc = s[0];
+#pragma unroll
+                for (int c = 1; c < KP; ++c) sc = lane == c ? s[c] : sc;
+                const TX xn = (br[t] - sc) / dr[t];
+                xout[i * KP + lane] = xn;
+                xl[t] = xn;
+                if (a.fused && r == 1) {
+                    // the set-up kernel's checks of this row
+                    if (lane == 0 && dr[t] == TX(0))
+                        __hip_atomic_fetch_min(&ctl->bad_zero, i, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    else if (lane == 0 && !isfinite(dr[t]))
+                        __hip_atomic_fetch_min(&ctl->bad_nonfinite, i, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (!isfinite(br[t]) || !isfinite(xo[t]))
+                        __hip_atomic_fetch_min(&ctl->bad_rhs, i, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+                const double dd = fabs((double)xn - (double)xo[t]);
+                const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                dmax = db > dmax ? db : dmax;
+                xmax = mb > xmax ? mb : xmax;
+                sq += dd * dd;
+            }
+        }
+        dmax = lane_max(dmax);
+        xmax = lane_max(xmax);
+        sq = lane_sum(sq);
+        if (lane == 0) {
+            red_d[wave] = dmax;
+            red_m[wave] = xmax;
+            red_s[wave] = sq;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            Slot* sl = &a.slots[r % 3];
+            uint64_t D = 0, M = 0;
+            double Q = 0.0;
+            for (int w = 0; w < W; ++w) {
+                D = red_d[w] > D ? red_d[w] : D;
+                M = red_m[w] > M ? red_m[w] : M;
+                Q += red_s[w];
+            }
+            __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&sl->xmax_bits, M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.parts[(size_t)(r % 3) * kMaxParts + blockIdx.x], Q,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (blockIdx.x == 0) {
+                // slot (r + 1) % 3 was last read in the decision of sweep
+                // r - 2, which every workgroup took (at the start of sweep
+                // r - 1) before barrier r - 1
+                Slot* nx = &a.slots[(r + 1) % 3];
+                __hip_atomic_store(&nx->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&nx->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // grid barrier r: every workgroup's statistics and rows of x^(r)
+            // precede its arrival (release); the wait ends with an acquire
+            __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = (uint32_t)G * (uint32_t)r;
+            const uint64_t t0 = wall_clock64();
+            bool ok = true;
+            while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   target) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((int64_t)(wall_clock64() - t0) > a.spin_limit) {
+                    ok = false;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (!ok) {
+                __hip_atomic_store(&ctl->stop_sweep, r, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctl->stop, (uint32_t)STOP_TIMEOUT, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                if (a.hctl != nullptr)
+                    __hip_atomic_store(&a.hctl->timeout, 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            s_go = ok;
+        }
+        __syncthreads();
+        if (!s_go) break;
+    }
+}
+
+template <typename TA, typename TX, int KP, int NP>
+static const void* small_reg_one(int* rpw) {
+    constexpr int r = small_reg_rpw<TA, TX, KP, NP>();
+    if constexpr (r == 0) {
+        return nullptr;
+    } else {
+        *rpw = r;
+        return (const void*)k_small_reg<TA, TX, KP, NP>;
+    }
+}
+
+template <typename TA, typename TX, int KP>
+static const void* small_reg_fn(int np, int* rpw) {
+    switch (np) {
+        case 1: return small_reg_one<TA, TX, KP, 1>(rpw);
+        case 2: return small_reg_one<TA, TX, KP, 2>(rpw);
+        case 4: return small_reg_one<TA, TX, KP, 4>(rpw);
+        case 8: return small_reg_one<TA, TX, KP, 8>(rpw);
+        case 16: return small_reg_one<TA, TX, KP, 16>(rpw);
+        default: return nullptr;
+    }
+}
+
+static const void* small_reg_pick(int32_t a_dtype, int kp, int np, int* rpw) {
+    if (a_dtype == 0)
+        return kp == 1 ? small_reg_fn<double, double, 1>(np, rpw)
+                       : small_reg_fn<double, double, 2>(np, rpw);
+    if (a_dtype == 1)
+        return kp == 1 ? small_reg_fn<float, float, 1>(np, rpw)
+                       : small_reg_fn<float, float, 2>(np, rpw);
+    if (a_dtype == 2)
+        return kp == 1 ? small_reg_fn<bf16_t, float, 1>(np, rpw)
+                       : small_reg_fn<bf16_t, float, 2>(np, rpw);
+    return nullptr;
+}
+
+int small_reg_np(int32_t a_dtype, int64_t n) {
+    const int64_t v = a_dtype == 0 ? 2 : (a_dtype == 1 ? 4 : 8);
+    const int64_t need = (n + 64 * v - 1) / (64 * v);
+    int np = 1;
+    while (np < need) np *= 2;
+    return np <= 16 ? np : 0;
+}
+
+int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np) {
+    int rpw = 0;
+    return (kp == 1 || kp == 2) && small_reg_pick(a_dtype, kp, np, &rpw) ? rpw : 0;
+}
+
+hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int grid,
+                            hipStream_t s) {
+    int rpw = 0;
+    const void* fn = (kp == 1 || kp == 2) ? small_reg_pick(a_dtype, kp, np, &rpw) : nullptr;
+    const int64_t per = (int64_t)4 * grid;
+    if (!fn || grid < 1 || grid > kMaxParts || small_reg_np(a_dtype, a.n) > np ||
+        (a.n + per - 1) / per > rpw)
+        return hipErrorInvalidValue;
+    SmallArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s);
+}
+
 template <typename TA, typename TX, int KP>
 static const void* small_fn(bool aligned) {
     return aligned ? (const void*)k_small<TA, TX, KP, true> : (const void*)k_small<TA, TX, KP, false>;

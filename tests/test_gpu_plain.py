@@ -28,7 +28,7 @@ def test_c1_parity(jac):
     say("c1 n=512 f64")
     X, info = jac.solve(dev(A), dev(B), tol=1e-10, max_iter=1000)
     assert info["status"] == jac.OK, info
-    assert info["kernel"] == 128  # every sweep in one launch of the small-system kernel
+    assert info["kernel"] == 129  # every sweep in one launch, A held in registers
     assert tie_margin(A, B, 1e-10, io["iterations"]) > 1e-6
     assert info["iterations"] == io["iterations"] == 9
     assert rel_err(host(X), xo) <= REL_F64
@@ -318,15 +318,29 @@ def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
     Bd = torch.from_numpy(np.asarray(B)).to(vdt).cuda()
     xo, io = oracle.jacobi(Ap, Bp, tol=tol, max_iter=500)
     out = {}
-    for mode in ("small", "vector"):
-        # every size of this test fits the small kernel's LDS: force it, or turn it off
-        monkeypatch.setenv("JACOBI_SMALL_MAX", "4096" if mode == "small" else "0")
+    for mode in ("small", "lds", "vector"):
+        # every size of this test fits the small kernel's LDS: force it (the
+        # register-resident variant where the rows fit, else the LDS one), or
+        # force its LDS variant, or turn it off
+        monkeypatch.setenv("JACOBI_SMALL_MAX", "0" if mode == "vector" else "4096")
+        monkeypatch.setenv("JACOBI_SMALL_REG", "0" if mode == "lds" else "1")
         say("small-system kernel", dtype, n, k, pad, mode)
         out[mode] = (jac.solve(Ad, Bd, tol=tol, max_iter=500),
                      jac.solve(Ad, Bd, tol=0.0, max_iter=7, norm="l2"))
+    monkeypatch.delenv("JACOBI_SMALL_REG")
     (Xs, inf_s), (Ls, linf_s) = out["small"]
+    (Xd, inf_d), (Ld, linf_d) = out["lds"]
     (Xv, inf_v), (Lv, linf_v) = out["vector"]
-    assert inf_s["kernel"] == 128 and inf_v["kernel"] == 0
+    assert inf_s["kernel"] in (128, 129) and inf_d["kernel"] == 128 and inf_v["kernel"] == 0
+    # the rows of every wave fit its registers except for FP64 n = 2048, k = 2
+    assert (inf_s["kernel"] == 129) == (not (dtype == "f64" and n == 2048 and k == 2))
+    # both variants take the same products in the same order: the same bits
+    # (the Euclidean distance adds one partial sum per workgroup, and the
+    # variants differ in workgroup count: equal to rounding)
+    assert torch.equal(Xs, Xd) and inf_s["iterations"] == inf_d["iterations"]
+    assert inf_s["final_delta"] == inf_d["final_delta"]
+    assert torch.equal(Ls, Ld)
+    assert abs(linf_s["final_delta"] - linf_d["final_delta"]) <= 1e-13 * linf_d["final_delta"]
     assert inf_s["status"] == inf_v["status"] == jac.OK, (inf_s, inf_v)
     assert abs(inf_s["iterations"] - inf_v["iterations"]) <= (0 if dtype == "f64" else 1)
     if dtype == "f64" and tie_margin(A, B, tol, io["iterations"]) > 1e-6:
@@ -344,4 +358,20 @@ def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
     monkeypatch.setenv("JACOBI_SMALL_MAX", "4096")
     X2, inf2 = jac.solve(Ad, Bd, tol=tol, max_iter=500)
     assert torch.equal(X2, Xs) and inf2["iterations"] == inf_s["iterations"]
+    # the fused launch (set-up, checks and copy-out in the register kernel,
+    # outcome written to the host) equals the separate set-up, read-back and
+    # copy-out bitwise, from zero and from a given X0, over 3 sweeps and to tol
+    x0 = torch.from_numpy(np.random.default_rng(n + k).uniform(-1, 1, size=(n, k))).to(vdt).cuda()
+    got = {}
+    for fz in ("1", "0"):
+        monkeypatch.setenv("JACOBI_SMALL_FUSED", fz)
+        say("small-system kernel fused", fz, dtype, n, k, pad)
+        got[fz] = [jac.solve(Ad, Bd, x, tol=t, max_iter=m)
+                   for x in (None, x0) for t, m in ((tol, 500), (0.0, 3))]
+    monkeypatch.delenv("JACOBI_SMALL_FUSED")
+    for (Xf, i_f), (Xu, i_u) in zip(got["1"], got["0"]):
+        assert i_f["kernel"] == i_u["kernel"] == inf_s["kernel"]
+        assert torch.equal(Xf, Xu), (dtype, n, k)
+        assert (i_f["status"], i_f["iterations"], i_f["final_delta"]) == \
+            (i_u["status"], i_u["iterations"], i_u["final_delta"])
     monkeypatch.delenv("JACOBI_SMALL_MAX")
