@@ -149,8 +149,14 @@ class Context:
 
 def _stream_handle(stream, device):
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream(device)
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:  # the current stream's handle without a Stream object
+        idx = device.index if getattr(device, "index", None) is not None else \
+            torch.cuda.current_device()
+        return ctypes.c_void_p(raw(idx))
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
 def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
