@@ -565,58 +565,82 @@ __global__ __launch_bounds__(256) void k_small_reg(SmallArgs a) {
         if (!sweep) break;
         uint64_t dmax = 0, xmax = 0;
         double sq = 0.0;
+        // Rows in chunks of up to four, all rows of a chunk at once (rows
+        // t >= nr hold zeros): their products, lane sums and divisions
+        // overlap; each row's own order of operations is unchanged.
+        constexpr int CH = RPW < 4 ? RPW : 4;
 #pragma unroll
-        for (int t = 0; t < RPW; ++t) {
-            if (t >= nr) break;
-            const int64_t i = i0 + di * t;
-            TX s[KP];
+        for (int t0 = 0; t0 < RPW; t0 += CH) {
+            if (t0 >= nr) break;
+            TX s[CH][KP];
 #pragma unroll
-            for (int c = 0; c < KP; ++c) s[c] = TX(0);
+            for (int j = 0; j < CH; ++j)
+#pragma unroll
+                for (int c = 0; c < KP; ++c) s[j][c] = TX(0);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int64_t c0 = ((int64_t)lane + 64 * p) * V;
                 if (c0 < n) {
-                    TX v[V];
-                    u32x4 u = ar[t][p];
-                    // BF16: unpack in every sweep; hoisted out of the loop,
-                    // the widened values would take twice the registers
-                    if constexpr (sizeof(TA) == 2) asm volatile("" : "+v"(u));
-                    unpack_piece<TA, TX>(u, v);
 #pragma unroll
-                    for (int e = 0; e < V; ++e) {
-                        if (c0 + e < n) {
+                    for (int j = 0; j < CH; ++j) {
+                        if (t0 + j >= RPW) break;
+                        TX v[V];
+                        u32x4 u = ar[t0 + j][p];
+                        // BF16: unpack in every sweep; hoisted out of the
+                        // loop, the widened values would take twice the
+                        // registers
+                        if constexpr (sizeof(TA) == 2) asm volatile("" : "+v"(u));
+                        unpack_piece<TA, TX>(u, v);
 #pragma unroll
-                            for (int c = 0; c < KP; ++c) s[c] += v[e] * xv[p][e * KP + c];
+                        for (int e = 0; e < V; ++e) {
+                            if (c0 + e < n) {
+#pragma unroll
+                                for (int c = 0; c < KP; ++c)
+                                    s[j][c] += v[e] * xv[p][e * KP + c];
+                            }
                         }
                     }
                 }
             }
+            // the lane sums of lane_sum, interleaved over the chunk's rows
 #pragma unroll
-            for (int c = 0; c < KP; ++c) s[c] = lane_sum(s[c]);
-            if (lane < k) {
-                TX sc = s[0];
+            for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
-                for (int c = 1; c < KP; ++c) sc = lane == c ? s[c] : sc;
+                for (int j = 0; j < CH; ++j)
+#pragma unroll
+                    for (int c = 0; c < KP; ++c) s[j][c] += __shfl_xor(s[j][c], o, 64);
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int t = t0 + j;
+                if (t >= RPW) break;
+                const int64_t i = i0 + di * t;
+                const bool live = t < nr && lane < k;
+                TX sc = s[j][0];
+#pragma unroll
+                for (int c = 1; c < KP; ++c) sc = lane == c ? s[j][c] : sc;
                 const TX xn = (br[t] - sc) / dr[t];
-                xout[i * KP + lane] = xn;
                 xl[t] = xn;
-                if (a.fused && r == 1) {
-                    // the set-up kernel's checks of this row
-                    if (lane == 0 && dr[t] == TX(0))
-                        __hip_atomic_fetch_min(&ctl->bad_zero, i, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    else if (lane == 0 && !isfinite(dr[t]))
-                        __hip_atomic_fetch_min(&ctl->bad_nonfinite, i, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    if (!isfinite(br[t]) || !isfinite(xo[t]))
-                        __hip_atomic_fetch_min(&ctl->bad_rhs, i, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                if (live) {
+                    xout[i * KP + lane] = xn;
+                    if (a.fused && r == 1) {
+                        // the set-up kernel's checks of this row
+                        if (lane == 0 && dr[t] == TX(0))
+                            __hip_atomic_fetch_min(&ctl->bad_zero, i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        else if (lane == 0 && !isfinite(dr[t]))
+                            __hip_atomic_fetch_min(&ctl->bad_nonfinite, i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        if (!isfinite(br[t]) || !isfinite(xo[t]))
+                            __hip_atomic_fetch_min(&ctl->bad_rhs, i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
                 const double dd = fabs((double)xn - (double)xo[t]);
-                const uint64_t db = dbits(dd), mb = dbits(fabs((double)xn));
+                const uint64_t db = live ? dbits(dd) : 0;
+                const uint64_t mb = live ? dbits(fabs((double)xn)) : 0;
                 dmax = db > dmax ? db : dmax;
                 xmax = mb > xmax ? mb : xmax;
-                sq += dd * dd;
+                sq += live ? dd * dd : 0.0;  // + 0.0 leaves the sum's bits as they are
             }
         }
         dmax = lane_max(dmax);
