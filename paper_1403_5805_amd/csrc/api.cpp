@@ -350,25 +350,37 @@ constexpr double kSmallMaxBytes = 12.0 * 1024 * 1024;
 
 // Fewest workgroups with which every wave's rows of an n-row system fit the
 // register variant's registers, or 0 when they do not fit in max_grid.
+// Eight waves per workgroup (four rows each, half the workgroups at the grid
+// barrier) for FP32 and BF16 A where that variant exists and fits, four for
+// FP64 (per solve, us, four / eight waves: FP64 n = 512 81 / 83; FP32 n =
+// 1024 74 / 65; BF16 n = 2048 96 / 83); JACOBI_SMALL_WAVES=4|8 overrides.
 static int64_t small_reg_min_grid(int32_t a_dtype, int64_t n, int kp, int64_t max_grid,
-                                  int* np_out, int* rpw_out) {
+                                  int* np_out, int* rpw_out, int* waves_out) {
     const char* renv = getenv("JACOBI_SMALL_REG");
     if (renv && atoi(renv) == 0) return 0;
     const int np = small_reg_np(a_dtype, n);
-    const int rpw = np ? small_reg_rows_per_wave(a_dtype, kp, np) : 0;
-    if (rpw <= 0) return 0;
-    const int64_t need = std::max<int64_t>(1, (n + 4 * (int64_t)rpw - 1) / (4 * (int64_t)rpw));
-    if (need > max_grid) return 0;
-    if (np_out) *np_out = np;
-    if (rpw_out) *rpw_out = rpw;
-    return need;
+    if (np == 0) return 0;
+    const char* wenv = getenv("JACOBI_SMALL_WAVES");
+    const int pref = wenv ? (atoi(wenv) == 8 ? 8 : 4) : (a_dtype == JACOBI_F64 ? 4 : 8);
+    for (const int waves : {pref, 4}) {
+        const int rpw = small_reg_rows_per_wave(a_dtype, kp, np, waves);
+        if (rpw <= 0) continue;
+        const int64_t per = (int64_t)waves * rpw;
+        const int64_t need = std::max<int64_t>(1, (n + per - 1) / per);
+        if (need > max_grid) continue;
+        if (np_out) *np_out = np;
+        if (rpw_out) *rpw_out = rpw;
+        if (waves_out) *waves_out = waves;
+        return need;
+    }
+    return 0;
 }
 
 static bool small_eligible(int32_t a_dtype, int64_t n, int kp, int num_cus) {
     const char* env = getenv("JACOBI_SMALL_MAX");
     if (env && n > atoll(env)) return false;
     if (small_reg_min_grid(a_dtype, n, kp, std::min<int64_t>(num_cus, kMaxParts), nullptr,
-                           nullptr) > 0)
+                           nullptr, nullptr) > 0)
         return true;
     if (n > small_max_rows(a_dtype, kp)) return false;
     return env || (double)n * (double)n * (double)dtype_bytes(a_dtype) <= kSmallMaxBytes;
@@ -382,12 +394,12 @@ static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, 
                                bool aligned, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
                                double* delta_out, double* xmax_out, bool* reg_out) {
     const int64_t max_grid = std::min<int64_t>(w.num_cus, kMaxParts);
-    int np = 0, rpw = 0;
-    const int64_t reg_grid = small_reg_min_grid(a_dtype, sa.n, kp, max_grid, &np, &rpw);
+    int np = 0, rpw = 0, waves = 4;
+    const int64_t reg_grid = small_reg_min_grid(a_dtype, sa.n, kp, max_grid, &np, &rpw, &waves);
     const bool reg = reg_grid > 0;
-    // rows per workgroup: 16 (4 per wave) for the register variant, 8 for the
-    // LDS one, measured best at n = 512
-    int64_t rows = reg ? 16 : 8;
+    // rows per workgroup: 4 per wave for the register variant, 8 (2 per wave)
+    // for the LDS one, measured best at n = 512
+    int64_t rows = reg ? 4 * waves : 8;
     if (const char* env = getenv("JACOBI_SMALL_ROWS")) rows = std::max<int64_t>(1, atoll(env));
     int grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, (sa.n + rows - 1) / rows));
     if (reg) grid = (int)std::max<int64_t>(grid, reg_grid);
@@ -402,7 +414,7 @@ static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, 
     if (sa.fused && !reg) return JACOBI_ERR_INTERNAL;  // the caller checked the fit
     if (sa.fused) w.sc.h_ctl->timeout = 0;  // host write, before the launch
     if (reg)
-        HIP_TRY(launch_small_reg(a_dtype, sa, kp, np, grid, s));
+        HIP_TRY(launch_small_reg(a_dtype, sa, kp, np, waves, grid, s));
     else
         HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
     *reg_out = reg;
@@ -445,7 +457,7 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
     const bool fused = small && o.max_iter >= 1 && w.h_ctl_dev != nullptr && x0_packed &&
                        !(fenv && atoi(fenv) == 0) &&
                        small_reg_min_grid(a_dtype, n, kp, std::min<int64_t>(w.num_cus, kMaxParts),
-                                          nullptr, nullptr) > 0;
+                                          nullptr, nullptr, nullptr) > 0;
     if (w.ev_begin) HIP_TRY(hipEventRecord(w.ev_begin, s));
     HIP_TRY(launch_init_ctl(ctl, w.slots, 1, s));
     if (!fused)

@@ -130,9 +130,10 @@ hipError_t launch_small(int32_t a_dtype, const SmallArgs& a, int kp, bool aligne
 // Register-resident variant (k_small_reg): np = 16-byte pieces per lane and
 // row (a power of two, 0 if n needs more than 16), rows per wave it holds.
 int small_reg_np(int32_t a_dtype, int64_t n);
-int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np);
-hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int grid,
-                            hipStream_t s);
+// waves = 4 or 8 per workgroup (8 only for np <= 4); 0 rows: no such variant.
+int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np, int waves);
+hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int waves,
+                            int grid, hipStream_t s);
 
 // Host-side launch configuration chosen per call.
 struct LaunchCfg {

@@ -270,14 +270,17 @@ __global__ __launch_bounds__(256) void k_small(SmallArgs a) {
 // products, their order, the lane sums, the update and the statistics are
 // those of k_small, so both kernels give the same bits.
 
-// Rows per wave (at most 8) that a budget of 192 32-bit registers per lane
-// holds beside the iterate's pieces, 0 if not one row fits.
-template <typename TA, typename TX, int KP, int NP>
+// Rows per wave that the register budget holds beside the iterate's pieces,
+// 0 if not one row fits: 192 32-bit registers per lane and at most 8 rows
+// with W = 4 waves per workgroup (one wave per SIMD, up to 512 registers),
+// 96 and at most 4 rows with W = 8 (two waves per SIMD, up to 256 each).
+template <typename TA, typename TX, int KP, int NP, int W>
 constexpr int small_reg_rpw() {
     constexpr int V = Piece<TA, TX>::V;
     constexpr int xv = NP * V * KP * (int)sizeof(TX) / 4;
-    constexpr int r = (192 - xv) / (4 * NP);
-    return r < 1 ? 0 : (r > 8 ? 8 : r);
+    constexpr int r = ((W == 4 ? 192 : 96) - xv) / (4 * NP);
+    constexpr int cap = W == 4 ? 8 : 4;
+    return r < 1 ? 0 : (r > cap ? cap : r);
 }
 
 template <typename TA, typename TX>
@@ -340,11 +343,10 @@ __device__ __forceinline__ void unpack_piece<bf16_t, float>(const u32x4 u, float
     }
 }
 
-template <typename TA, typename TX, int KP, int NP>
-__global__ __launch_bounds__(256) void k_small_reg(SmallArgs a) {
-    constexpr int W = 4;
+template <typename TA, typename TX, int KP, int NP, int W>
+__global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
     constexpr int V = Piece<TA, TX>::V;
-    constexpr int RPW = small_reg_rpw<TA, TX, KP, NP>();
+    constexpr int RPW = small_reg_rpw<TA, TX, KP, NP, W>();
     __shared__ uint64_t red_d[W], red_m[W];
     __shared__ double red_s[W];
     __shared__ uint32_t s_go, s_stop;
@@ -706,39 +708,50 @@ __global__ __launch_bounds__(256) void k_small_reg(SmallArgs a) {
     }
 }
 
-template <typename TA, typename TX, int KP, int NP>
+template <typename TA, typename TX, int KP, int NP, int W>
 static const void* small_reg_one(int* rpw) {
-    constexpr int r = small_reg_rpw<TA, TX, KP, NP>();
+    constexpr int r = small_reg_rpw<TA, TX, KP, NP, W>();
     if constexpr (r == 0) {
         return nullptr;
     } else {
         *rpw = r;
-        return (const void*)k_small_reg<TA, TX, KP, NP>;
+        return (const void*)k_small_reg<TA, TX, KP, NP, W>;
     }
 }
 
+// Eight waves per workgroup only where a row takes at most four pieces per
+// lane (n <= 512 FP64, 1024 FP32, 2048 BF16).
 template <typename TA, typename TX, int KP>
-static const void* small_reg_fn(int np, int* rpw) {
+static const void* small_reg_fn(int np, int waves, int* rpw) {
+    if (waves == 8) {
+        switch (np) {
+            case 1: return small_reg_one<TA, TX, KP, 1, 8>(rpw);
+            case 2: return small_reg_one<TA, TX, KP, 2, 8>(rpw);
+            case 4: return small_reg_one<TA, TX, KP, 4, 8>(rpw);
+            default: return nullptr;
+        }
+    }
+    if (waves != 4) return nullptr;
     switch (np) {
-        case 1: return small_reg_one<TA, TX, KP, 1>(rpw);
-        case 2: return small_reg_one<TA, TX, KP, 2>(rpw);
-        case 4: return small_reg_one<TA, TX, KP, 4>(rpw);
-        case 8: return small_reg_one<TA, TX, KP, 8>(rpw);
-        case 16: return small_reg_one<TA, TX, KP, 16>(rpw);
+        case 1: return small_reg_one<TA, TX, KP, 1, 4>(rpw);
+        case 2: return small_reg_one<TA, TX, KP, 2, 4>(rpw);
+        case 4: return small_reg_one<TA, TX, KP, 4, 4>(rpw);
+        case 8: return small_reg_one<TA, TX, KP, 8, 4>(rpw);
+        case 16: return small_reg_one<TA, TX, KP, 16, 4>(rpw);
         default: return nullptr;
     }
 }
 
-static const void* small_reg_pick(int32_t a_dtype, int kp, int np, int* rpw) {
+static const void* small_reg_pick(int32_t a_dtype, int kp, int np, int waves, int* rpw) {
     if (a_dtype == 0)
-        return kp == 1 ? small_reg_fn<double, double, 1>(np, rpw)
-                       : small_reg_fn<double, double, 2>(np, rpw);
+        return kp == 1 ? small_reg_fn<double, double, 1>(np, waves, rpw)
+                       : small_reg_fn<double, double, 2>(np, waves, rpw);
     if (a_dtype == 1)
-        return kp == 1 ? small_reg_fn<float, float, 1>(np, rpw)
-                       : small_reg_fn<float, float, 2>(np, rpw);
+        return kp == 1 ? small_reg_fn<float, float, 1>(np, waves, rpw)
+                       : small_reg_fn<float, float, 2>(np, waves, rpw);
     if (a_dtype == 2)
-        return kp == 1 ? small_reg_fn<bf16_t, float, 1>(np, rpw)
-                       : small_reg_fn<bf16_t, float, 2>(np, rpw);
+        return kp == 1 ? small_reg_fn<bf16_t, float, 1>(np, waves, rpw)
+                       : small_reg_fn<bf16_t, float, 2>(np, waves, rpw);
     return nullptr;
 }
 
@@ -750,22 +763,23 @@ int small_reg_np(int32_t a_dtype, int64_t n) {
     return np <= 16 ? np : 0;
 }
 
-int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np) {
+int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np, int waves) {
     int rpw = 0;
-    return (kp == 1 || kp == 2) && small_reg_pick(a_dtype, kp, np, &rpw) ? rpw : 0;
+    return (kp == 1 || kp == 2) && small_reg_pick(a_dtype, kp, np, waves, &rpw) ? rpw : 0;
 }
 
-hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int grid,
-                            hipStream_t s) {
+hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int waves,
+                            int grid, hipStream_t s) {
     int rpw = 0;
-    const void* fn = (kp == 1 || kp == 2) ? small_reg_pick(a_dtype, kp, np, &rpw) : nullptr;
-    const int64_t per = (int64_t)4 * grid;
+    const void* fn =
+        (kp == 1 || kp == 2) ? small_reg_pick(a_dtype, kp, np, waves, &rpw) : nullptr;
+    const int64_t per = (int64_t)waves * grid;
     if (!fn || grid < 1 || grid > kMaxParts || small_reg_np(a_dtype, a.n) > np ||
         (a.n + per - 1) / per > rpw)
         return hipErrorInvalidValue;
     SmallArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * waves), args, 0, s);
 }
 
 template <typename TA, typename TX, int KP>

@@ -369,6 +369,14 @@ def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
         got[fz] = [jac.solve(Ad, Bd, x, tol=t, max_iter=m)
                    for x in (None, x0) for t, m in ((tol, 500), (0.0, 3))]
     monkeypatch.delenv("JACOBI_SMALL_FUSED")
+    # four and eight waves per workgroup (where both exist): the same bits
+    for wv in ("4", "8"):
+        monkeypatch.setenv("JACOBI_SMALL_WAVES", wv)
+        say("small-system kernel waves", wv, dtype, n, k, pad)
+        Xw, iw = jac.solve(Ad, Bd, tol=tol, max_iter=500)
+        assert torch.equal(Xw, Xs) and iw["iterations"] == inf_s["iterations"], (wv, dtype, n, k)
+        assert iw["final_delta"] == inf_s["final_delta"]
+    monkeypatch.delenv("JACOBI_SMALL_WAVES")
     for (Xf, i_f), (Xu, i_u) in zip(got["1"], got["0"]):
         assert i_f["kernel"] == i_u["kernel"] == inf_s["kernel"]
         assert torch.equal(Xf, Xu), (dtype, n, k)
