@@ -232,6 +232,13 @@ def main() -> int:
             "kernel": "k_sweep<float,float,KT=1,R=2,U=2,W=8>",
             "avg_kernel_us": round(avg_ms * 1e3, 2), "kernel_launches": launches,
             "bytes_per_launch": per_sweep, "timing": how}
+    # the achievable read ceiling: the library's read-only stream probe over
+    # the same 1 GiB matrix (after the timed region)
+    probe = jac.stream_probe(A, reps=5)
+    roof["achievable_GBps"] = round(probe["GBps"], 1)
+    roof["frac_of_achievable"] = round(achieved / probe["GBps"], 4)
+    roof["achievable_probe"] = (f"jacobi_stream_probe: 16-byte non-temporal reads of A, "
+                                f"{probe['wg_per_cu']} workgroups per CU, best of 5")
 
     cpu = None
     model, _ = _host_cpu()

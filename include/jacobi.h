@@ -347,6 +347,19 @@ JACOBI_API jacobi_status jacobi_solve_noalloc(int64_t n, int64_t k, int32_t a_dt
  * context.  Returns JACOBI_OK. */
 JACOBI_API jacobi_status jacobi_shutdown(void);
 
+/* Achievable HBM read bandwidth (a measurement utility, beside the 8 TB/s
+ * published peak): streams the device buffer buf (bytes, 16-byte aligned,
+ * on the current device; not modified) with 16-byte non-temporal loads,
+ * the load width of the sweep's stream of A, in a grid-stride read-only
+ * kernel at 2, 4, 8 and 16 workgroups of 256 threads per CU, reps timed
+ * launches each (HIP events on `stream`, one untimed launch before), and
+ * returns the fastest rate in *gbps (bytes / time / 1e9) and its workgroups
+ * per CU in *wg_per_cu (may be null).  Waits for the stream.  Use a buffer
+ * larger than the caches (the 256 MB MALL): 1 GiB gives the HBM rate. */
+JACOBI_API jacobi_status jacobi_stream_probe(const void* buf, int64_t bytes, int32_t reps,
+                                             hipStream_t stream, double* gbps,
+                                             int32_t* wg_per_cu);
+
 /* Human-readable name of a status code (static string). */
 JACOBI_API const char* jacobi_status_string(int32_t status);
 

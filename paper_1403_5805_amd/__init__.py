@@ -20,8 +20,8 @@ from ._lib import (BF16, CANCELLED, DIVERGED, ERR_DEVICE, ERR_INTERNAL, ERR_INVA
                    ERR_NONFINITE_INPUT, ERR_OUT_OF_MEMORY, ERR_REJECTED, ERR_ZERO_DIAGONAL, F32,
                    F64, NOT_CONVERGED, OK, PENDING, Info, Options)
 
-__all__ = ["solve", "solve_noalloc", "solve_batched", "Batch", "Server", "Matrix",
-           "status_string", "last_error", "Context",
+__all__ = ["solve", "solve_noalloc", "stream_probe", "solve_batched", "Batch", "Server",
+           "Matrix", "status_string", "last_error", "Context",
            "OK", "NOT_CONVERGED", "DIVERGED", "PENDING", "CANCELLED", "ERR_INVALID_ARG",
            "ERR_ZERO_DIAGONAL", "ERR_NONFINITE_INPUT", "ERR_OUT_OF_MEMORY", "ERR_DEVICE",
            "ERR_REJECTED", "ERR_INTERNAL", "F64", "F32", "BF16"]
@@ -214,6 +214,23 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
         if raise_on_error:
             raise RuntimeError(f"jacobi_solve failed: {d['status_name']}: {d['error']}")
     return out, d
+
+
+def stream_probe(buf, *, reps: int = 5, stream=None) -> dict:
+    """jacobi_stream_probe: the achievable HBM read rate over a device tensor
+    (read only; at least 16 bytes; larger than the caches for the HBM rate).
+    Returns {"GBps": fastest rate, "wg_per_cu": its launch shape}."""
+    lib = _lib.load()
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("stream_probe needs a contiguous device tensor")
+    g = ctypes.c_double()
+    w = ctypes.c_int32()
+    st = lib.jacobi_stream_probe(_ptr(buf), buf.numel() * buf.element_size(), int(reps),
+                                 _stream_handle(stream, buf.device), ctypes.byref(g),
+                                 ctypes.byref(w))
+    if st != OK:
+        raise RuntimeError(f"jacobi_stream_probe: {status_string(st)} {last_error()}")
+    return {"GBps": g.value, "wg_per_cu": w.value}
 
 
 def solve_noalloc(A, B, x0=None, *, out=None, stream=None, raise_on_error: bool = False,

@@ -198,6 +198,9 @@ def load():
                                           ctypes.POINTER(Options), vp, ctypes.POINTER(Info)]
     lib.jacobi_matrix_destroy.restype = i32
     lib.jacobi_matrix_destroy.argtypes = [vp]
+    lib.jacobi_stream_probe.restype = i32
+    lib.jacobi_stream_probe.argtypes = [vp, i64, i32, vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(i32)]
     _lib = lib
     atexit.register(_shutdown)
     return lib

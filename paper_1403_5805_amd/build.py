@@ -28,7 +28,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch=
 SOURCES = ["sweep.hip", "batched.hip", "small.hip", "resid.hip", "convert.hip", "api.cpp",
            "refine.cpp",
            "batch_api.cpp", "plan.cpp", "resid_api.cpp", "arena.cpp", "serve.cpp",
-           "noalloc.cpp", "prepared.cpp"]
+           "noalloc.cpp", "prepared.cpp", "probe.hip"]
 
 
 def _compile(src: str) -> str:

@@ -383,3 +383,21 @@ def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
         assert (i_f["status"], i_f["iterations"], i_f["final_delta"]) == \
             (i_u["status"], i_u["iterations"], i_u["final_delta"])
     monkeypatch.delenv("JACOBI_SMALL_MAX")
+
+
+def test_stream_probe(jac):
+    """The achievable-read probe: a rate between a fraction of the published
+    HBM peak and a little above it on a buffer larger than the caches, the
+    buffer unchanged, bad arguments refused."""
+    import torch
+    buf = torch.arange(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
+    ref = buf.clone()
+    say("stream probe")
+    p = jac.stream_probe(buf, reps=2)
+    assert 1000.0 < p["GBps"] < 8800.0, p
+    assert p["wg_per_cu"] in (2, 4, 8, 16)
+    assert torch.equal(buf, ref)
+    with pytest.raises(ValueError):
+        jac.stream_probe(buf[::2])
+    with pytest.raises(RuntimeError):
+        jac.stream_probe(buf[:1], reps=1)  # 4 bytes: below one 16-byte piece

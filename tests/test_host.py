@@ -44,7 +44,7 @@ def _declared():
 
 def test_exports_match_header(lib):
     declared = _declared()
-    assert len(declared) == 19
+    assert len(declared) == 20
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], check=True, capture_output=True,
                          text=True).stdout
     exported = sorted(ln.split()[-1] for ln in out.splitlines() if " T " in ln)
