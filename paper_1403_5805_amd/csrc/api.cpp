@@ -330,7 +330,7 @@ jacobi_status solve_plain_locked(jacobi_ctx* c, int64_t n, int64_t k, int32_t a_
     HIP_TRY(c->w0.ensure(sx * n * kp));
     HIP_TRY(c->w1.ensure(sx * n * kp));
     PlainWs w{sweep_ctl(c), c->slots, c->parts, c->diag.p, c->w0.p, c->w1.p,
-              c->ev_begin, c->ev_end, c->num_cus, c->h_ctl_dev};
+              c->ev_begin, c->ev_end, c->num_cus, c->h_ctl_dev, &c->small_chain};
     return solve_plain_vec(w, n, k, a_dtype, A, lda, B, ldb, X0, X, ldx, o, s, info);
 }
 
@@ -392,7 +392,8 @@ static bool small_eligible(int32_t a_dtype, int64_t n, int kp, int num_cus) {
 // caller waits.
 static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, int kp,
                                bool aligned, hipStream_t s, uint32_t* stop_out, int32_t* k_out,
-                               double* delta_out, double* xmax_out, bool* reg_out) {
+                               double* delta_out, double* xmax_out, bool* reg_out,
+                               int* grid_out) {
     const int64_t max_grid = std::min<int64_t>(w.num_cus, kMaxParts);
     int np = 0, rpw = 0, waves = 4;
     const int64_t reg_grid = small_reg_min_grid(a_dtype, sa.n, kp, max_grid, &np, &rpw, &waves);
@@ -418,6 +419,7 @@ static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, 
     else
         HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
     *reg_out = reg;
+    *grid_out = grid;
     if (sa.fused) return JACOBI_OK;
     HIP_TRY(hipMemcpyAsync(w.sc.h_ctl, w.sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -458,8 +460,21 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
                        !(fenv && atoi(fenv) == 0) &&
                        small_reg_min_grid(a_dtype, n, kp, std::min<int64_t>(w.num_cus, kMaxParts),
                                           nullptr, nullptr, nullptr) > 0;
+    // A fused launch after a fused launch on the same control block skips
+    // k_init_ctl (the kernel continues the barrier count and the slot
+    // rotation the previous one left); any other use of the block, a timeout
+    // or invalid input makes the next one initialise it.
+    SmallChain* const chain = w.chain;
+    const bool chained = fused && chain != nullptr && chain->ready;
+    if (chain) chain->ready = false;
     if (w.ev_begin) HIP_TRY(hipEventRecord(w.ev_begin, s));
-    HIP_TRY(launch_init_ctl(ctl, w.slots, 1, s));
+    if (!chained) {
+        HIP_TRY(launch_init_ctl(ctl, w.slots, 1, s));
+        if (chain) {
+            chain->bar_base = 0;
+            chain->slot_base = 0;
+        }
+    }
     if (!fused)
         HIP_TRY(launch_setup(a_dtype, A, lda, B, ldb, X0, ldx, n, (int)k, kp, w.diag, w.w0,
                              w.w1, ctl, s));
@@ -513,8 +528,12 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
             sa.X = X;
             sa.ldx = ldx;
             sa.hctl = w.h_ctl_dev;
+            sa.bar_base = chain ? chain->bar_base : 0u;
+            sa.slot_base = chain ? chain->slot_base : 0;
         }
-        st = run_small(w, a_dtype, sa, kp, a.aligned != 0, s, &stop, &K, &delta, &xmax, &reg);
+        int grid = 0;
+        st = run_small(w, a_dtype, sa, kp, a.aligned != 0, s, &stop, &K, &delta, &xmax, &reg,
+                       &grid);
         if (st == JACOBI_OK && fused) {
             if (w.ev_begin && w.ev_end) {
                 HIP_TRY(hipEventRecord(w.ev_end, s));
@@ -539,6 +558,13 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
                 info->final_delta = -1.0;
                 set_error("input validation failed at row %lld", (long long)info->bad_index);
                 return vs;
+            }
+            if (chain) {
+                // every workgroup arrived at barriers 1 .. sweeps_done; the
+                // slot after the last computed sweep's is clear
+                chain->bar_base += (uint32_t)grid * (uint32_t)h.sweeps_done;
+                chain->slot_base = (chain->slot_base + h.sweeps_done) % 3;
+                chain->ready = true;
             }
             K = h.stop != STOP_RUNNING ? h.stop_sweep : o.max_iter;
             info->iterations = K;

@@ -21,6 +21,14 @@ struct DevBuf {
     void release();
 };
 
+// Barrier count and slot rotation left by the last fused small-system
+// launch on a control block (see k_small_reg).
+struct SmallChain {
+    bool ready = false;
+    uint32_t bar_base = 0;
+    int32_t slot_base = 0;
+};
+
 // Variant of a batched launch; every variant gives bitwise the same results.
 struct BatchTune {
     int shape = 1;   // 0 wide (two workgroups per CU), 1 deep (one)
@@ -53,6 +61,11 @@ struct jacobi_ctx {
     double* parts = nullptr;      // device partial sums [3][kMaxParts]
     jac::Ctl* h_ctl = nullptr;    // pinned host mirror of ctl
     jac::Ctl* h_ctl_dev = nullptr;  // its device-visible address (null: not mapped)
+    // State of ctl and slots left by the last fused small-system launch, so
+    // that the next one can skip k_init_ctl: the barrier count it ended at and
+    // the slot rotation that leaves its first slot clear (ready = false after
+    // any other use of ctl, a timeout or invalid input: initialise again).
+    jac::SmallChain small_chain;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     std::vector<hipEvent_t> prof_ev;
     // plain solve
@@ -116,6 +129,7 @@ struct PlainWs {
     // device-visible address of sc.h_ctl, or null (then the small-system
     // kernel's outcome is copied back from sc.ctl)
     Ctl* h_ctl_dev = nullptr;
+    SmallChain* chain = nullptr;  // the context's, or null: initialise every time
 };
 
 // Padded column count of the iterate buffers for k right-hand sides.

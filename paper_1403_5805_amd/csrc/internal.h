@@ -115,7 +115,9 @@ struct SmallArgs {
     // X itself; hctl (if not null, device-visible host memory) receives the
     // final control block.  Needs cap >= 1.
     int32_t fused;
-    int32_t pad2;
+    int32_t slot_base;  // fused: sweep r uses slot (slot_base + r) % 3
+    uint32_t bar_base;  // fused: barrier r completes at count bar_base + G r (wrapping)
+    int32_t pad3;
     const void* X0;    // TX, n x k packed (ldx0 = k, 16-byte aligned), or null: x^(0) = 0
     int64_t ldx0;
     void* X;           // TX, n x k (ldx)

@@ -49,6 +49,7 @@ jacobi_status solve_refine(jacobi_ctx* c, int64_t n, int64_t k, const void* A, i
                            const void* B, int64_t ldb, const void* X0, void* X, int64_t ldx,
                            const jacobi_options& o, hipStream_t s, jacobi_info* info,
                            const PreparedLo* pre) {
+    c->small_chain.ready = false;  // this path re-initialises ctl and its slots
     const int32_t lo = o.sweep_dtype;
     if ((lo != JACOBI_F32 && lo != JACOBI_BF16) || !(o.inner_rel_tol >= 0.0) ||
         !(o.refine_tol >= 0.0) || o.max_inner < 1 || o.max_outer < 0) {

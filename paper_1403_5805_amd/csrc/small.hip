@@ -359,11 +359,20 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
     const TX* B = (const TX*)a.B;
     const TX* diag = (const TX*)a.diag;
     Ctl* ctl = a.ctl;
-    if (tid == 0)
-        s_go = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-               STOP_RUNNING;
-    __syncthreads();
-    if (!s_go) return;  // invalid input: no sweep
+    // a separate set-up kernel may have found invalid input (fused: the
+    // checks are this launch's, and the stop word is left as it was)
+    if (!a.fused) {
+        if (tid == 0)
+            s_go = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                   STOP_RUNNING;
+        __syncthreads();
+        if (!s_go) return;  // invalid input: no sweep
+    }
+    // Fused launches may follow one another on the same control block without
+    // a k_init_ctl in between: the barrier count then starts at bar_base and
+    // sweep r uses slot (slot_base + r) % 3, which the host sets so that the
+    // first sweep's slot is one the previous launch left clear.
+    const int sb = a.slot_base;
     const int64_t i0 = wave + (int64_t)W * blockIdx.x;
     const int64_t di = (int64_t)W * G;
     // rows t < nr of this wave; the host guarantees nr <= RPW
@@ -487,7 +496,7 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
         if (r > 1) {
             if (tid == 0) {
                 const int q = r - 1;
-                const Slot* sl = &a.slots[q % 3];
+                const Slot* sl = &a.slots[(sb + q) % 3];
                 uint32_t st = STOP_RUNNING;
                 const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT));
@@ -497,7 +506,7 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                 if (a.norm == 1) {
                     double S = 0.0;  // workgroup order
                     for (int g = 0; g < G; ++g)
-                        S += __hip_atomic_load(&a.parts[(size_t)(q % 3) * kMaxParts + g],
+                        S += __hip_atomic_load(&a.parts[(size_t)((sb + q) % 3) * kMaxParts + g],
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     delta = sqrt(S);
                 }
@@ -655,7 +664,7 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
         }
         __syncthreads();
         if (tid == 0) {
-            Slot* sl = &a.slots[r % 3];
+            Slot* sl = &a.slots[(sb + r) % 3];
             uint64_t D = 0, M = 0;
             double Q = 0.0;
             for (int w = 0; w < W; ++w) {
@@ -665,13 +674,13 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
             }
             __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_max(&sl->xmax_bits, M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.parts[(size_t)(r % 3) * kMaxParts + blockIdx.x], Q,
+            __hip_atomic_store(&a.parts[(size_t)((sb + r) % 3) * kMaxParts + blockIdx.x], Q,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (blockIdx.x == 0) {
-                // slot (r + 1) % 3 was last read in the decision of sweep
-                // r - 2, which every workgroup took (at the start of sweep
-                // r - 1) before barrier r - 1
-                Slot* nx = &a.slots[(r + 1) % 3];
+                // slot (sb + r + 1) % 3 was last read in the decision of
+                // sweep r - 2, which every workgroup took (at the start of
+                // sweep r - 1) before barrier r - 1
+                Slot* nx = &a.slots[(sb + r + 1) % 3];
                 __hip_atomic_store(&nx->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&nx->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
@@ -680,11 +689,12 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
             // grid barrier r: every workgroup's statistics and rows of x^(r)
             // precede its arrival (release); the wait ends with an acquire
             __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t target = (uint32_t)G * (uint32_t)r;
+            const uint32_t target = a.bar_base + (uint32_t)G * (uint32_t)r;
             const uint64_t t0 = wall_clock64();
             bool ok = true;
-            while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   target) {
+            while ((int32_t)(__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT) -
+                             target) < 0) {
                 __builtin_amdgcn_s_sleep(1);
                 if ((int64_t)(wall_clock64() - t0) > a.spin_limit) {
                     ok = false;

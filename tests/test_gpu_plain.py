@@ -401,3 +401,55 @@ def test_stream_probe(jac):
         jac.stream_probe(buf[::2])
     with pytest.raises(RuntimeError):
         jac.stream_probe(buf[:1], reps=1)  # 4 bytes: below one 16-byte piece
+
+
+def test_small_fused_launches_in_a_row(jac, monkeypatch):
+    """Fused small-system solves one after another on one context, each
+    continuing the barrier count and slot rotation the previous launch left
+    (no k_init_ctl between them): different sizes, dtypes, k, norms and caps,
+    with an invalid input and a refinement solve (which re-initialise the
+    control block) in between, the whole sequence twice.  Every result equals
+    the same solve with the separate set-up (JACOBI_SMALL_FUSED=0) bitwise."""
+    import torch
+    ctx = jac.Context(0)
+    cases = []
+    for n, k, seed in ((512, 1, 1), (200, 2, 2), (37, 1, 3), (1254, 2, 4)):
+        A, _, B = synth.dominant(n, k, 6100 + seed)
+        cases.append(("f64", dev(A), dev(B)))
+    for n, k, seed, dt in ((1000, 1, 5, torch.float32), (2048, 2, 6, torch.bfloat16)):
+        A, _, B = synth.dominant_f32(n, k, 6100 + seed, synth.ADDITIVE, 1.0, 2.0)
+        cases.append(("f32" if dt == torch.float32 else "bf16",
+                      torch.from_numpy(A).to(dt).cuda(), torch.from_numpy(B).cuda()))
+    opts = [dict(tol=1e-10, max_iter=500), dict(tol=0.0, max_iter=5, norm="l2"),
+            dict(tol=0.0, max_iter=1), dict(tol=1e-11, max_iter=500, norm="l2"),
+            dict(tol=1e-6, max_iter=500), dict(tol=1e-6, max_iter=4)]
+    Az, _, Bz = synth.dominant(300, 1, 6107)
+    Az[123, 123] = 0.0
+    Ar, _, Br = synth.dominant(256, 1, 6108)
+
+    def sequence():
+        out = []
+        for rep in range(2):
+            for i, ((dt, Ad, Bd), o) in enumerate(zip(cases, opts)):
+                say("fused chain", rep, i, dt, tuple(Ad.shape), Bd.shape[1])
+                out.append(jac.solve(Ad, Bd, ctx=ctx, **o))
+                if i == 2:
+                    out.append(jac.solve(dev(Az), dev(Bz), ctx=ctx))
+                if i == 3:
+                    out.append(jac.solve(dev(Ar), dev(Br), ctx=ctx, mode="refine",
+                                         sweep_dtype="f32", refine_tol=1e-12))
+        return out
+    fused = sequence()
+    monkeypatch.setenv("JACOBI_SMALL_FUSED", "0")
+    sep = sequence()
+    monkeypatch.delenv("JACOBI_SMALL_FUSED")
+    for (Xf, i_f), (Xs, i_s) in zip(fused, sep):
+        assert (i_f["status"], i_f["iterations"], i_f["final_delta"], i_f["bad_index"]) == \
+            (i_s["status"], i_s["iterations"], i_s["final_delta"], i_s["bad_index"])
+        if i_f["status"] >= 0:
+            assert torch.equal(Xf, Xs)
+    assert [i["status"] for _, i in fused].count(jac.ERR_ZERO_DIAGONAL) == 2
+    # every case but FP64 n = 1254, k = 2 (rows too long for the registers:
+    # the LDS variant) ran fused in the register kernel, twice
+    assert [i["kernel"] for _, i in fused].count(129) == 10
+    ctx.close()
