@@ -1,9 +1,12 @@
 // Small systems in one launch (gfx950).
 //
 // The plain path runs one kernel launch per sweep, which for a system of a
-// few MiB costs more than the sweep itself.  This kernel runs every sweep of
-// one system (k <= 2 right-hand sides, iterate small enough for LDS) in a
-// single launch of G co-resident workgroups, G <= the CU count:
+// few MiB costs more than the sweep itself.  Two kernels here run every
+// sweep of one system (k <= 2 right-hand sides) in a single launch of G
+// co-resident workgroups, G <= the CU count: k_small_reg (further below),
+// which holds each wave's rows of A in registers and can also take the
+// set-up's and the copy-out's place, and k_small, its fallback for rows too
+// long for the registers, described here (iterate small enough for LDS):
 //   * each sweep stages x^(r-1) (n x kp values, row-major) in LDS;
 //   * wave w of workgroup g takes rows w + 4 g, w + 4 g + 4 G, ...; the 64
 //     lanes split a row's columns in 16-byte pieces (one vector load when the
