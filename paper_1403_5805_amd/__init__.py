@@ -123,6 +123,25 @@ def make_options(tol=1e-8, max_iter=10000, norm="inf", mode="plain", sweep_dtype
     return o
 
 
+_OPTIONS_CACHE: dict = {}
+
+
+def _options(opts: dict) -> Options:
+    """make_options(**opts), kept per distinct keyword set (the library reads
+    the struct through a const pointer and never changes it)."""
+    try:
+        key = tuple(sorted(opts.items()))
+        o = _OPTIONS_CACHE.get(key)
+    except TypeError:  # an unhashable value: build it every time
+        return make_options(**opts)
+    if o is None:
+        o = make_options(**opts)
+        if len(_OPTIONS_CACHE) >= 256:
+            _OPTIONS_CACHE.clear()
+        _OPTIONS_CACHE[key] = o
+    return o
+
+
 class Context:
     """A solver context bound to one device (owns reusable workspaces)."""
 
@@ -182,23 +201,23 @@ def solve(A, B, x0=None, *, out=None, ctx: Context | None = None, stream=None,
     if B.shape[0] != n or B.dim() > 2:
         raise ValueError("B must be (n,) or (n, k)")
     dt = _a_dtype(A)
-    _check_operand(A, "A", A.device, A.dtype, (n, n))
+    lda = _check_operand(A, "A", A.device, A.dtype, (n, n))
     vdt = _vec_dtype(dt, opts.get("mode", "plain"))
-    _check_operand(B, "B", A.device, vdt, B.shape)
+    ldb = _check_operand(B, "B", A.device, vdt, B.shape)
     if out is None:
         out = torch.empty((n,) if vec else (n, k), dtype=B.dtype, device=B.device)
-    _check_operand(out, "out", A.device, vdt, B.shape)
+    ldx = _check_operand(out, "out", A.device, vdt, B.shape)
     if x0 is not None:
-        _check_operand(x0, "x0", A.device, vdt, B.shape)
-    if x0 is not None and not vec and _ld(x0) != _ld(out):
-        # X0 is read with out's leading dimension
-        x0 = torch.empty((n, _ld(out)), dtype=vdt, device=A.device)[:, :k].copy_(x0)
+        ld0 = _check_operand(x0, "x0", A.device, vdt, B.shape)
+        if not vec and ld0 != ldx:
+            # X0 is read with out's leading dimension
+            x0 = torch.empty((n, ldx), dtype=vdt, device=A.device)[:, :k].copy_(x0)
     noalloc = _noalloc
-    o = make_options(**opts)
+    o = _options(opts)
     info = Info()
-    args = (n, k, dt, _ptr(A), _ld(A), _ptr(B), _ld(B) if not vec else 1,
-            _ptr(x0) if x0 is not None else None, _ptr(out), _ld(out) if not vec else 1,
-            ctypes.byref(o), _stream_handle(stream, A.device), ctypes.byref(info))
+    args = (n, k, dt, _ptr(A), lda, _ptr(B), ldb, _ptr(x0) if x0 is not None else None,
+            _ptr(out), ldx, ctypes.byref(o), _stream_handle(stream, A.device),
+            ctypes.byref(info))
     if noalloc:
         if ctx is not None:
             raise ValueError("the no-allocation entry point takes no context")
