@@ -452,4 +452,15 @@ def test_small_fused_launches_in_a_row(jac, monkeypatch):
     # every case but FP64 n = 1254, k = 2 (rows too long for the registers:
     # the LDS variant) ran fused in the register kernel, twice
     assert [i["kernel"] for _, i in fused].count(129) == 10
+    # X written from registers into a strided view (ldx = k + 3), with X0
+    # absent (fused) and given with that leading dimension (separate set-up)
+    A, _, B = synth.dominant(300, 2, 6109)
+    Ad, Bd = dev(A), dev(B)
+    ref, iref = jac.solve(Ad, Bd, ctx=ctx, tol=1e-10, max_iter=500)
+    for x0 in (None, torch.zeros((300, 5), dtype=torch.float64, device="cuda")[:, :2]):
+        say("fused strided out", x0 is None)
+        big = torch.full((300, 5), 7.5, dtype=torch.float64, device="cuda")
+        X, info = jac.solve(Ad, Bd, x0, out=big[:, :2], ctx=ctx, tol=1e-10, max_iter=500)
+        assert info["kernel"] == 129 and info["iterations"] == iref["iterations"]
+        assert torch.equal(big[:, :2], ref) and bool((big[:, 2:] == 7.5).all())
     ctx.close()
