@@ -41,18 +41,62 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
+// Exchange of a value between lanes for step S of the wave reductions:
+// S = 0, 1 swap within groups of four lanes (DPP quad_perm, lane ^ 1 and
+// lane ^ 2), S = 2 the other group of four of a half row (DPP
+// row_half_mirror), S = 3 the other half of a row of 16 (DPP row_mirror),
+// S = 4, 5 lane ^ 16 and lane ^ 32 (lane permutes).  After steps 0 and 1
+// every lane of a group of four holds the same value (and after step 2 every
+// lane of a half row), so the mirrors pair the same partial results as
+// lane ^ 4 and lane ^ 8 would; the DPP steps are register moves instead of
+// the LDS-routed permutes.
+template <int S>
+__device__ __forceinline__ uint32_t xchg32(uint32_t v) {
+    // DPP controls: quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
+    // row_half_mirror = 0x141, row_mirror = 0x140
+    constexpr int kCtrl[4] = {0xB1, 0x4E, 0x141, 0x140};
+    if constexpr (S < 4)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl[S], 0xf, 0xf, false);
+    else
+        return (uint32_t)__shfl_xor((int)v, S == 4 ? 16 : 32, 64);
+}
+template <int S>
+__device__ __forceinline__ float xchg(float v) {
+    return __uint_as_float(xchg32<S>(__float_as_uint(v)));
+}
+template <int S>
+__device__ __forceinline__ double xchg(double v) {
+    const uint32_t lo = xchg32<S>((uint32_t)__double2loint(v));
+    const uint32_t hi = xchg32<S>((uint32_t)__double2hiint(v));
+    return __hiloint2double((int)hi, (int)lo);
+}
+template <int S>
+__device__ __forceinline__ uint64_t xchg(uint64_t v) {
+    const uint32_t lo = xchg32<S>((uint32_t)v);
+    const uint32_t hi = xchg32<S>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum over the wave in the fixed step order above: every lane ends with the
+// same bits (each step adds two equal-by-symmetry partners, a + b = b + a).
 template <typename T>
 __device__ __forceinline__ T lane_sum(T v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += xchg<0>(v);
+    v += xchg<1>(v);
+    v += xchg<2>(v);
+    v += xchg<3>(v);
+    v += xchg<4>(v);
+    v += xchg<5>(v);
     return v;
 }
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 __device__ __forceinline__ uint64_t lane_max(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint64_t w = (uint64_t)__shfl_xor((long long)v, o, 64);
-        v = w > v ? w : v;
-    }
+    v = umax64(v, xchg<0>(v));
+    v = umax64(v, xchg<1>(v));
+    v = umax64(v, xchg<2>(v));
+    v = umax64(v, xchg<3>(v));
+    v = umax64(v, xchg<4>(v));
+    v = umax64(v, xchg<5>(v));
     return v;
 }
 
@@ -616,13 +660,17 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                     }
                 }
             }
-            // the lane sums of lane_sum, interleaved over the chunk's rows
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1)
-#pragma unroll
-                for (int j = 0; j < CH; ++j)
-#pragma unroll
-                    for (int c = 0; c < KP; ++c) s[j][c] += __shfl_xor(s[j][c], o, 64);
+            // the steps of lane_sum, interleaved over the chunk's rows
+#define JAC_SUM_STEP(S_)                                        \
+    _Pragma("unroll") for (int j = 0; j < CH; ++j)              \
+        _Pragma("unroll") for (int c = 0; c < KP; ++c) s[j][c] += xchg<S_>(s[j][c]);
+            JAC_SUM_STEP(0)
+            JAC_SUM_STEP(1)
+            JAC_SUM_STEP(2)
+            JAC_SUM_STEP(3)
+            JAC_SUM_STEP(4)
+            JAC_SUM_STEP(5)
+#undef JAC_SUM_STEP
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
                 const int t = t0 + j;
@@ -797,7 +845,8 @@ hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np,
 
 template <typename TA, typename TX, int KP>
 static const void* small_fn(bool aligned) {
-    return aligned ? (const void*)k_small<TA, TX, KP, true> : (const void*)k_small<TA, TX, KP, false>;
+    return aligned ? (const void*)k_small<TA, TX, KP, true>
+                   : (const void*)k_small<TA, TX, KP, false>;
 }
 
 int64_t small_max_rows(int32_t a_dtype, int32_t kp) {
