@@ -394,7 +394,7 @@ template <typename TA, typename TX, int KP, int NP, int W>
 __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
     constexpr int V = Piece<TA, TX>::V;
     constexpr int RPW = small_reg_rpw<TA, TX, KP, NP, W>();
-    __shared__ uint64_t red_d[W], red_m[W];
+    __shared__ uint64_t red_d[W];
     __shared__ double red_s[W];
     __shared__ uint32_t s_go, s_stop;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -547,8 +547,6 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                 uint32_t st = STOP_RUNNING;
                 const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT));
-                const double xm = bitsd(__hip_atomic_load(&sl->xmax_bits, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT));
                 double delta = dm;
                 if (a.norm == 1) {
                     double S = 0.0;  // workgroup order
@@ -574,8 +572,6 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                 if (blockIdx.x == 0) {
                     __hip_atomic_store(&ctl->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&ctl->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(&ctl->sweeps_done, q, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     if (st != STOP_RUNNING) {
@@ -594,8 +590,6 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                         __hip_atomic_store(&h->sweeps_done, q, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_SYSTEM);
                         __hip_atomic_store(&h->last_delta_bits, dbits(delta), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_SYSTEM);
-                        __hip_atomic_store(&h->last_xmax_bits, dbits(xm), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_SYSTEM);
                         __hip_atomic_store(&h->bad_zero, bad_z, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_SYSTEM);
@@ -621,7 +615,10 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
             }
         }
         if (!sweep) break;
-        uint64_t dmax = 0, xmax = 0;
+        // the distance's statistics (max|x_new| is not needed on this path:
+        // the plain solve reports no iterate size; the sum of squares only
+        // for the Euclidean distance)
+        uint64_t dmax = 0;
         double sq = 0.0;
         // Rows in chunks of up to four, all rows of a chunk at once (rows
         // t >= nr hold zeros): their products, lane sums and divisions
@@ -699,42 +696,35 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                 }
                 const double dd = fabs((double)xn - (double)xo[t]);
                 const uint64_t db = live ? dbits(dd) : 0;
-                const uint64_t mb = live ? dbits(fabs((double)xn)) : 0;
                 dmax = db > dmax ? db : dmax;
-                xmax = mb > xmax ? mb : xmax;
                 sq += live ? dd * dd : 0.0;  // + 0.0 leaves the sum's bits as they are
             }
         }
         dmax = lane_max(dmax);
-        xmax = lane_max(xmax);
-        sq = lane_sum(sq);
+        if (a.norm == 1) sq = lane_sum(sq);
         if (lane == 0) {
             red_d[wave] = dmax;
-            red_m[wave] = xmax;
             red_s[wave] = sq;
         }
         __syncthreads();
         if (tid == 0) {
             Slot* sl = &a.slots[(sb + r) % 3];
-            uint64_t D = 0, M = 0;
+            uint64_t D = 0;
             double Q = 0.0;
             for (int w = 0; w < W; ++w) {
                 D = red_d[w] > D ? red_d[w] : D;
-                M = red_m[w] > M ? red_m[w] : M;
                 Q += red_s[w];
             }
             __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(&sl->xmax_bits, M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.parts[(size_t)((sb + r) % 3) * kMaxParts + blockIdx.x], Q,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.norm == 1)
+                __hip_atomic_store(&a.parts[(size_t)((sb + r) % 3) * kMaxParts + blockIdx.x], Q,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (blockIdx.x == 0) {
                 // slot (sb + r + 1) % 3 was last read in the decision of
                 // sweep r - 2, which every workgroup took (at the start of
                 // sweep r - 1) before barrier r - 1
                 Slot* nx = &a.slots[(sb + r + 1) % 3];
                 __hip_atomic_store(&nx->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&nx->xmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             // grid barrier r: every workgroup's statistics and rows of x^(r)
