@@ -413,13 +413,13 @@ static jacobi_status run_small(const PlainWs& w, int32_t a_dtype, SmallArgs sa, 
     sa.spin_limit = (int64_t)rate_khz * 1000 * 20;  // 20 s
     sa.aligned = aligned ? 1 : 0;
     if (sa.fused && !reg) return JACOBI_ERR_INTERNAL;  // the caller checked the fit
+    *grid_out = grid;
     if (sa.fused) w.sc.h_ctl->timeout = 0;  // host write, before the launch
     if (reg)
         HIP_TRY(launch_small_reg(a_dtype, sa, kp, np, waves, grid, s));
     else
         HIP_TRY(launch_small(a_dtype, sa, kp, aligned, grid, s));
     *reg_out = reg;
-    *grid_out = grid;
     if (sa.fused) return JACOBI_OK;
     HIP_TRY(hipMemcpyAsync(w.sc.h_ctl, w.sc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -521,6 +521,10 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
         sa.parts = w.parts;
         sa.tol = o.tol;
         sa.norm = o.norm;
+        // JACOBI_SMALL_ATOMIC_GRID overrides the largest grid that gathers
+        // the distance's maximum with atomics (tuning and diagnosis)
+        sa.atomic_max_grid = kSmallAtomicMaxGrid;
+        if (const char* env = getenv("JACOBI_SMALL_ATOMIC_GRID")) sa.atomic_max_grid = atoi(env);
         if (fused) {
             sa.fused = 1;
             sa.X0 = X0;
@@ -560,10 +564,13 @@ jacobi_status solve_plain_vec(const PlainWs& w, int64_t n, int64_t k, int32_t a_
                 return vs;
             }
             if (chain) {
-                // every workgroup arrived at barriers 1 .. sweeps_done; the
-                // slot after the last computed sweep's is clear
+                // every workgroup arrived at barriers 1 .. sweeps_done; after
+                // a launch that used the slots, the one after the last
+                // computed sweep's is clear (a larger grid leaves them as
+                // they were)
                 chain->bar_base += (uint32_t)grid * (uint32_t)h.sweeps_done;
-                chain->slot_base = (chain->slot_base + h.sweeps_done) % 3;
+                if (grid <= sa.atomic_max_grid)
+                    chain->slot_base = (chain->slot_base + h.sweeps_done) % 3;
                 chain->ready = true;
             }
             K = h.stop != STOP_RUNNING ? h.stop_sweep : o.max_iter;

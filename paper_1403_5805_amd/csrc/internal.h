@@ -117,7 +117,7 @@ struct SmallArgs {
     int32_t fused;
     int32_t slot_base;  // fused: sweep r uses slot (slot_base + r) % 3
     uint32_t bar_base;  // fused: barrier r completes at count bar_base + G r (wrapping)
-    int32_t pad3;
+    int32_t atomic_max_grid;  // k_small_reg: grids up to this gather maxima with atomics
     const void* X0;    // TX, n x k packed (ldx0 = k, 16-byte aligned), or null: x^(0) = 0
     int64_t ldx0;
     void* X;           // TX, n x k (ldx)
@@ -129,6 +129,11 @@ struct SmallArgs {
 int64_t small_max_rows(int32_t a_dtype, int32_t kp);
 hipError_t launch_small(int32_t a_dtype, const SmallArgs& a, int kp, bool aligned, int grid,
                         hipStream_t s);
+// Default of SmallArgs::atomic_max_grid: k_small_reg grids of at most this
+// many workgroups gather the distance's maximum with atomics in the rotating
+// slots; larger ones store one word per workgroup and leave the slots
+// untouched (the host advances the slot rotation only after the former).
+constexpr int kSmallAtomicMaxGrid = 64;
 // Register-resident variant (k_small_reg): np = 16-byte pieces per lane and
 // row (a power of two, 0 if n needs more than 16), rows per wave it holds.
 int small_reg_np(int32_t a_dtype, int64_t n);

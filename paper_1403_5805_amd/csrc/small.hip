@@ -420,6 +420,9 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
     // sweep r uses slot (slot_base + r) % 3, which the host sets so that the
     // first sweep's slot is one the previous launch left clear.
     const int sb = a.slot_base;
+    // one atomic word gathers the distance's maximum on small grids; larger
+    // ones, where those atomics queue, store one word per workgroup
+    const bool atomic_max = G <= a.atomic_max_grid;
     const int64_t i0 = wave + (int64_t)W * blockIdx.x;
     const int64_t di = (int64_t)W * G;
     // rows t < nr of this wave; the host guarantees nr <= RPW
@@ -540,14 +543,35 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
             for (int t = 0; t < RPW; ++t)
                 xo[t] = (t < nr && lane < k) ? xin[(i0 + di * t) * KP + lane] : TX(0);
         }
-        if (r > 1) {
-            if (tid == 0) {
+        if (r > 1 && wave == 0) {
+            // the distance's maximum over the workgroups for sweep r - 1:
+            // the slot every workgroup folded its own into with an atomic
+            // maximum (grids of at most a.atomic_max_grid), else the
+            // workgroups' own stored maxima (each stored before barrier
+            // r - 1), four loads per lane in flight
+            const uint64_t* dp =
+                (const uint64_t*)(a.parts + (size_t)((sb + r - 1) % 3) * kMaxParts + kMaxParts / 2);
+            uint64_t pd = 0;
+            if (atomic_max && lane == 0)
+                pd = __hip_atomic_load(&a.slots[(sb + r - 1) % 3].dmax_bits, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            for (int g0 = 0; !atomic_max && g0 < G; g0 += 256) {
+                uint64_t v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int g = g0 + lane + 64 * j;
+                    v[j] = g < G ? __hip_atomic_load(&dp[g], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pd = v[j] > pd ? v[j] : pd;
+            }
+            pd = lane_max(pd);
+            if (lane == 0) {
                 const int q = r - 1;
-                const Slot* sl = &a.slots[(sb + q) % 3];
                 uint32_t st = STOP_RUNNING;
-                const double dm = bitsd(__hip_atomic_load(&sl->dmax_bits, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT));
-                double delta = dm;
+                double delta = bitsd(pd);
                 if (a.norm == 1) {
                     double S = 0.0;  // workgroup order
                     for (int g = 0; g < G; ++g)
@@ -602,6 +626,8 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
                 s_go = st == STOP_RUNNING;
                 s_stop = st;
             }
+        }
+        if (r > 1) {
             __syncthreads();
             if (!s_go || !sweep) {
                 const uint32_t st = s_stop;
@@ -708,25 +734,32 @@ __global__ __launch_bounds__(W * 64) void k_small_reg(SmallArgs a) {
         }
         __syncthreads();
         if (tid == 0) {
-            Slot* sl = &a.slots[(sb + r) % 3];
             uint64_t D = 0;
             double Q = 0.0;
             for (int w = 0; w < W; ++w) {
                 D = red_d[w] > D ? red_d[w] : D;
                 Q += red_s[w];
             }
-            __hip_atomic_fetch_max(&sl->dmax_bits, D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (a.norm == 1)
-                __hip_atomic_store(&a.parts[(size_t)((sb + r) % 3) * kMaxParts + blockIdx.x], Q,
+            // this workgroup's maximum and partial sum of sweep r: an atomic
+            // maximum into slot (sb + r) % 3 on small grids (workgroup 0
+            // clears the slot after next, last read in the decision of sweep
+            // r - 2, which every workgroup took at the start of sweep r - 1,
+            // before barrier r - 1), else a plain store of its own, like the
+            // partial sum, in its words of parts slot (sb + r) % 3 (read after
+            // barrier r, overwritten in sweep r + 3, after barrier r + 2)
+            double* pr = a.parts + (size_t)((sb + r) % 3) * kMaxParts;
+            if (atomic_max) {
+                __hip_atomic_fetch_max(&a.slots[(sb + r) % 3].dmax_bits, D, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (blockIdx.x == 0)
+                    __hip_atomic_store(&a.slots[(sb + r + 1) % 3].dmax_bits, (uint64_t)0,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store((uint64_t*)(pr + kMaxParts / 2) + blockIdx.x, D,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (blockIdx.x == 0) {
-                // slot (sb + r + 1) % 3 was last read in the decision of
-                // sweep r - 2, which every workgroup took (at the start of
-                // sweep r - 1) before barrier r - 1
-                Slot* nx = &a.slots[(sb + r + 1) % 3];
-                __hip_atomic_store(&nx->dmax_bits, (uint64_t)0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (a.norm == 1)
+                __hip_atomic_store(pr + blockIdx.x, Q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // grid barrier r: every workgroup's statistics and rows of x^(r)
             // precede its arrival (release); the wait ends with an acquire
             __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
