@@ -821,6 +821,7 @@ static const void* small_reg_fn(int np, int waves, int* rpw) {
         case 2: return small_reg_one<TA, TX, KP, 2, 4>(rpw);
         case 4: return small_reg_one<TA, TX, KP, 4, 4>(rpw);
         case 8: return small_reg_one<TA, TX, KP, 8, 4>(rpw);
+        case 12: return small_reg_one<TA, TX, KP, 12, 4>(rpw);
         case 16: return small_reg_one<TA, TX, KP, 16, 4>(rpw);
         default: return nullptr;
     }
@@ -840,11 +841,13 @@ static const void* small_reg_pick(int32_t a_dtype, int kp, int np, int waves, in
 }
 
 int small_reg_np(int32_t a_dtype, int64_t n) {
+    // pieces per lane and row: 1, 2, 4, 8, 12 or 16 (12: rows of 9 to 12
+    // steps fit the registers where 16 would not, e.g. FP32 n = 3072)
     const int64_t v = a_dtype == 0 ? 2 : (a_dtype == 1 ? 4 : 8);
     const int64_t need = (n + 64 * v - 1) / (64 * v);
-    int np = 1;
-    while (np < need) np *= 2;
-    return np <= 16 ? np : 0;
+    for (const int np : {1, 2, 4, 8, 12, 16})
+        if (np >= need) return np;
+    return 0;
 }
 
 int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np, int waves) {

@@ -292,7 +292,8 @@ def test_c2_full_size_parity(jac):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,k,pad", [(1, 1, 0), (5, 2, 0), (37, 2, 1), (512, 1, 0),
-                                     (1000, 2, 3), (2048, 1, 0), (2048, 2, 1)])
+                                     (1000, 2, 3), (1500, 1, 0), (2048, 1, 0), (2048, 2, 1),
+                                     (3000, 1, 1)])
 def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
     """Systems of at most 2048 rows (one or two right-hand sides) run every
     sweep in one persistent launch, the small-system kernel; the per-sweep
@@ -332,8 +333,10 @@ def test_small_system_kernel(jac, monkeypatch, dtype, n, k, pad):
     (Xd, inf_d), (Ld, linf_d) = out["lds"]
     (Xv, inf_v), (Lv, linf_v) = out["vector"]
     assert inf_s["kernel"] in (128, 129) and inf_d["kernel"] == 128 and inf_v["kernel"] == 0
-    # the rows of every wave fit its registers except for FP64 n = 2048, k = 2
-    assert (inf_s["kernel"] == 129) == (not (dtype == "f64" and n == 2048 and k == 2))
+    # the rows of every wave fit its registers (12 pieces of 16 bytes per lane
+    # and row for FP64 n = 1500 and FP32 n = 3000) except for FP64 n = 2048,
+    # k = 2 and FP64 n = 3000
+    assert (inf_s["kernel"] == 129) == (not (dtype == "f64" and (n, k) in ((2048, 2), (3000, 1))))
     # both variants take the same products in the same order: the same bits
     # (the Euclidean distance adds one partial sum per workgroup, and the
     # variants differ in workgroup count: equal to rounding)
@@ -449,9 +452,9 @@ def test_small_fused_launches_in_a_row(jac, monkeypatch):
         if i_f["status"] >= 0:
             assert torch.equal(Xf, Xs)
     assert [i["status"] for _, i in fused].count(jac.ERR_ZERO_DIAGONAL) == 2
-    # every case but FP64 n = 1254, k = 2 (rows too long for the registers:
-    # the LDS variant) ran fused in the register kernel, twice
-    assert [i["kernel"] for _, i in fused].count(129) == 10
+    # every case ran fused in the register kernel, twice (FP64 n = 1254, k = 2
+    # with 12 pieces of 16 bytes per lane and row)
+    assert [i["kernel"] for _, i in fused].count(129) == 12
     # X written from registers into a strided view (ldx = k + 3), with X0
     # absent (fused) and given with that leading dimension (separate set-up)
     A, _, B = synth.dominant(300, 2, 6109)
