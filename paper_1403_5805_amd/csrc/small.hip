@@ -307,15 +307,17 @@ __global__ __launch_bounds__(256) void k_small(SmallArgs a) {
 
 // ---------------------------------------------------------------------------
 // Register-resident variant.  A does not change between sweeps and wave w of
-// workgroup g always owns the same rows (w + 4 g + 4 G t), so the wave loads
-// its rows once, before the first sweep, into registers: one 16-byte piece
-// of a row per lane and step of 64 pieces (NP steps cover the row), the
-// diagonal entry stored as zero, and b_i, a_ii beside them.  Every sweep
-// then reads only the iterate, straight into registers (a lane needs the
-// same NP pieces of x for every row it holds), all loads issued before the
-// first use: one memory round trip per sweep instead of one per piece.  The
-// products, their order, the lane sums, the update and the statistics are
-// those of k_small, so both kernels give the same bits.
+// workgroup g always owns the same rows (w + W g + W G t, W waves per
+// workgroup), so the wave loads its rows once, before the first sweep, into
+// registers: one 16-byte piece of a row per lane and step of 64 pieces (NP
+// steps cover the row), the diagonal entry stored as zero, and b_i, a_ii
+// beside them.  Every sweep then reads only the iterate, straight into
+// registers (a lane needs the same NP pieces of x for every row it holds),
+// all loads issued before the first use: one memory round trip per sweep
+// instead of one per piece.  The products, their order, the lane sums, the
+// update and the distance the stop test uses are those of k_small, so both
+// kernels give the same bits (only the statistics no decision needs are
+// left out).
 
 // Rows per wave that the register budget holds beside the iterate's pieces,
 // 0 if not one row fits: 192 32-bit registers per lane and at most 8 rows
