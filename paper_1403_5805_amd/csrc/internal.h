@@ -137,7 +137,7 @@ constexpr int kSmallAtomicMaxGrid = 64;
 // Register-resident variant (k_small_reg): np = 16-byte pieces per lane and
 // row (1, 2, 4, 8, 12 or 16; 0 if n needs more than 16), rows per wave it holds.
 int small_reg_np(int32_t a_dtype, int64_t n);
-// waves = 4 or 8 per workgroup (8 only for np <= 4); 0 rows: no such variant.
+// waves = 4 or 8 per workgroup (8 only for np <= 8); 0 rows: no such variant.
 int small_reg_rows_per_wave(int32_t a_dtype, int kp, int np, int waves);
 hipError_t launch_small_reg(int32_t a_dtype, const SmallArgs& a, int kp, int np, int waves,
                             int grid, hipStream_t s);

@@ -805,8 +805,9 @@ static const void* small_reg_one(int* rpw) {
     }
 }
 
-// Eight waves per workgroup only where a row takes at most four pieces per
-// lane (n <= 512 FP64, 1024 FP32, 2048 BF16).
+// Eight waves per workgroup only where a row takes at most eight pieces per
+// lane (n <= 1024 FP64, 2048 FP32, 4096 BF16; where the 96-register budget
+// holds too few rows for the grid, the host falls back to four waves).
 template <typename TA, typename TX, int KP>
 static const void* small_reg_fn(int np, int waves, int* rpw) {
     if (waves == 8) {
@@ -814,6 +815,7 @@ static const void* small_reg_fn(int np, int waves, int* rpw) {
             case 1: return small_reg_one<TA, TX, KP, 1, 8>(rpw);
             case 2: return small_reg_one<TA, TX, KP, 2, 8>(rpw);
             case 4: return small_reg_one<TA, TX, KP, 4, 8>(rpw);
+            case 8: return small_reg_one<TA, TX, KP, 8, 8>(rpw);
             default: return nullptr;
         }
     }
